@@ -1,0 +1,330 @@
+"""CPU oracle for the Barnes-Hut tree-code hot path (FP64, plain C + numpy).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the
+benchmark's CPU-baseline leg, never by the GPU library or its binding.  It
+shares no code with the HIP path.
+
+Steps (paper: Bedorf et al., SC14, arXiv:1412.0659):
+  bounding box + Morton keys    Sec. III.B.1 (space-filling-curve keys from
+                                the bounding box; Morton in place of
+                                Peano-Hilbert, the same octree cell set)
+  stable key sort               Table II "Sorting SFC" (numpy stable argsort)
+  octree build                  Sec. I.A (split octants until a cell holds at
+                                most 16 particles)
+  groups                        target groups of the group-wise walk
+  moments                       Sec. VI.A Eq. (1): mass, centre of mass and
+                                the 3x3 quadrupole
+  walk + forces                 Sec. I.A opening angle theta; Sec. VI.A
+                                Eq. (1)-(2); Plummer softening (Sec. IV)
+  direct summation              the theta -> 0 limit of Sec. I.A
+  leapfrog (KDK)                Sec. III.B.2 (second-order leap-frog)
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from .build import ensure_built
+
+NLEAF = 16
+NCRIT = 64
+NLEVELS = 22
+
+_lib = None
+
+_f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(ensure_built())
+        L.orc_num_threads.restype = _int
+        L.orc_bbox.argtypes = [_i64, _f32p, _f32p, _f32p, _f32p]
+        L.orc_keys.argtypes = [_i64, _f32p, _f32p, ctypes.c_float, _u64p]
+        L.orc_build.argtypes = [_i64, _u64p, _int, _i64, _i32p, _u64p, _i64p, _i64p, _i64p,
+                                _i32p, _i64p, _i64p]
+        L.orc_build.restype = _i64
+        L.orc_groups.argtypes = [_i64, _i64p, _i64p, _i32p, _i64p, _int, _i64p, _i64p, _i64p]
+        L.orc_groups.restype = _i64
+        L.orc_group_boxes.argtypes = [_i64, _i64p, _i64p, _f32p, _f32p, _f32p, _f32p, _f32p]
+        L.orc_moments.argtypes = [_i64, _i32p, _u64p, _i64p, _i64p, _i64p, _i32p, _f32p, _f32p,
+                                  _f32p, _f32p, _f32p, ctypes.c_float, _f64p, _f64p, _f64p,
+                                  _f64p, _f32p, _f32p, _f32p]
+        L.orc_open_radius.argtypes = [_i64, _f32p, _f32p, ctypes.c_float, _f32p]
+        L.orc_walk.argtypes = [_i64, _i64p, _i64p, _i64p, _f32p, _f32p, _i64, _i64p, _i64p,
+                               _i64p, _i32p, _f64p, _f64p, _f64p, _f32p, _f32p, _f32p, _f32p,
+                               _f32p, _f32p, ctypes.c_double, _f64p, _f64p, _i64p, _i64p,
+                               _i64p, _i64p]
+        L.orc_direct.argtypes = [_i64, _f64p, _f64p, _i64, _i64p, ctypes.c_double, _f64p, _f64p]
+        L.orc_expansion.argtypes = [_i64, _f64p, ctypes.c_double, _f64p, _f64p, ctypes.c_double,
+                                    _f64p, _f64p]
+        _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --- O1/O2/O3 ----------------------------------------------------------------
+
+def bbox(pos):
+    pos = _f32(pos).reshape(-1, 3)
+    lo = np.zeros(3, np.float32)
+    side = np.zeros(1, np.float32)
+    scale = np.zeros(1, np.float32)
+    lib().orc_bbox(pos.shape[0], pos, lo, side, scale)
+    return lo, np.float32(side[0]), np.float32(scale[0])
+
+
+def morton_keys(pos, lo, scale):
+    pos = _f32(pos).reshape(-1, 3)
+    out = np.empty(pos.shape[0], np.uint64)
+    lib().orc_keys(pos.shape[0], pos, _f32(lo), ctypes.c_float(scale), out)
+    return out
+
+
+def sort_keys(keys):
+    """Stable ascending sort; equal keys keep their input order."""
+    return np.argsort(keys, kind="stable")
+
+
+# --- O4/O5 ---------------------------------------------------------------------
+
+def cell_capacity(n: int, nleaf: int = NLEAF) -> int:
+    """Upper bound on the cell count: at most n leaves (disjoint, non-empty)
+    plus, on each of the 21 levels that can hold internal cells, at most
+    n // (nleaf + 1) disjoint cells holding more than nleaf particles."""
+    return n + 21 * (n // (nleaf + 1)) + 1
+
+
+def build_cells(skeys, nleaf: int = NLEAF):
+    skeys = np.ascontiguousarray(skeys, dtype=np.uint64)
+    n = skeys.shape[0]
+    cap = cell_capacity(n, nleaf)
+    level = np.empty(cap, np.int32)
+    prefix = np.empty(cap, np.uint64)
+    begin = np.empty(cap, np.int64)
+    count = np.empty(cap, np.int64)
+    child0 = np.empty(cap, np.int64)
+    nchild = np.empty(cap, np.int32)
+    parent = np.empty(cap, np.int64)
+    ls = np.zeros(NLEVELS + 1, np.int64)
+    nc = lib().orc_build(n, skeys, nleaf, cap, level, prefix, begin, count, child0, nchild,
+                         parent, ls)
+    if nc < 0:
+        raise RuntimeError("cell capacity exceeded")
+    return dict(level=level[:nc].copy(), prefix=prefix[:nc].copy(), begin=begin[:nc].copy(),
+                count=count[:nc].copy(), child0=child0[:nc].copy(), nchild=nchild[:nc].copy(),
+                parent=parent[:nc].copy(), level_start=ls, ncell=int(nc))
+
+
+def make_groups(cells, ncrit: int = NCRIT):
+    nc = cells["ncell"]
+    n = int(cells["count"][0])
+    gbeg = np.empty(n, np.int64)
+    gcnt = np.empty(n, np.int64)
+    gcell = np.empty(n, np.int64)
+    ng = lib().orc_groups(nc, cells["begin"], cells["count"], cells["nchild"], cells["parent"],
+                          ncrit, gbeg, gcnt, gcell)
+    return gbeg[:ng].copy(), gcnt[:ng].copy(), gcell[:ng].copy()
+
+
+def group_boxes(gbeg, gcnt, x, y, z):
+    ng = gbeg.shape[0]
+    gc = np.empty(3 * ng, np.float32)
+    gh = np.empty(3 * ng, np.float32)
+    lib().orc_group_boxes(ng, gbeg, gcnt, _f32(x), _f32(y), _f32(z), gc, gh)
+    return gc.reshape(ng, 3), gh.reshape(ng, 3)
+
+
+# --- O6 --------------------------------------------------------------------------
+
+def moments(cells, x, y, z, m, lo, side):
+    nc = cells["ncell"]
+    M = np.empty(nc)
+    S = np.empty(3 * nc)
+    com = np.empty(3 * nc)
+    Q = np.empty(6 * nc)
+    comf = np.empty(3 * nc, np.float32)
+    lf = np.empty(nc, np.float32)
+    deltaf = np.empty(nc, np.float32)
+    lib().orc_moments(nc, cells["level"], cells["prefix"], cells["begin"], cells["count"],
+                      cells["child0"], cells["nchild"], _f32(x), _f32(y), _f32(z), _f32(m),
+                      _f32(lo), ctypes.c_float(side), M, S, com, Q, comf, lf, deltaf)
+    return dict(M=M, S=S.reshape(nc, 3), com=com.reshape(nc, 3), Q=Q.reshape(nc, 6),
+                comf=comf.reshape(nc, 3), lf=lf, deltaf=deltaf)
+
+
+def open_radius2(lf, deltaf, theta):
+    out = np.empty(lf.shape[0], np.float32)
+    lib().orc_open_radius(lf.shape[0], _f32(lf), _f32(deltaf), ctypes.c_float(theta), out)
+    return out
+
+
+# --- the whole tree ------------------------------------------------------------
+
+@dataclass
+class Tree:
+    n: int
+    lo: np.ndarray
+    side: np.float32
+    scale: np.float32
+    keys: np.ndarray       # caller order
+    perm: np.ndarray       # sorted slot -> caller index
+    skeys: np.ndarray
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    m: np.ndarray
+    cells: dict
+    gbeg: np.ndarray
+    gcnt: np.ndarray
+    gcell: np.ndarray
+    gc: np.ndarray
+    gh: np.ndarray
+    mom: dict
+
+    @property
+    def ngroups(self):
+        return int(self.gbeg.shape[0])
+
+    def group_of_sorted(self):
+        g = np.zeros(self.n, np.int64)
+        g[self.gbeg[1:]] = 1
+        return np.cumsum(g)
+
+
+def build_tree(pos, mass, nleaf: int = NLEAF, ncrit: int = NCRIT) -> Tree:
+    pos = _f32(pos).reshape(-1, 3)
+    mass = _f32(mass).reshape(-1)
+    n = pos.shape[0]
+    lo, side, scale = bbox(pos)
+    keys = morton_keys(pos, lo, scale)
+    perm = sort_keys(keys)
+    skeys = keys[perm]
+    sp = pos[perm]
+    x, y, z = (np.ascontiguousarray(sp[:, a]) for a in range(3))
+    m = np.ascontiguousarray(mass[perm])
+    cells = build_cells(skeys, nleaf)
+    gbeg, gcnt, gcell = make_groups(cells, ncrit)
+    gc, gh = group_boxes(gbeg, gcnt, x, y, z)
+    mom = moments(cells, x, y, z, m, lo, side)
+    return Tree(n, lo, side, scale, keys, perm, skeys, x, y, z, m, cells, gbeg, gcnt, gcell,
+                gc, gh, mom)
+
+
+def walk(tree: Tree, theta: float, eps: float, groups=None, diag=False):
+    """Tree forces for the targets of the listed groups (all groups by default).
+
+    Returns (acc[N,3], pot[N]) in caller order (NaN where not computed) and
+    per-group (npp, npc) counts (-1 where not walked).  With ``diag`` also
+    returns per-group (ncov, nself): particles covered by the interaction
+    lists and accepted cells holding a particle of the group."""
+    n = tree.n
+    ro2 = open_radius2(tree.mom["lf"], tree.mom["deltaf"], theta)
+    glist = np.arange(tree.ngroups, dtype=np.int64) if groups is None else \
+        np.ascontiguousarray(np.unique(groups), dtype=np.int64)
+    acc_s = np.full(3 * n, np.nan)
+    pot_s = np.full(n, np.nan)
+    npp = np.full(tree.ngroups, -1, np.int64)
+    npc = np.full(tree.ngroups, -1, np.int64)
+    ncov = np.full(tree.ngroups, -1, np.int64)
+    nself = np.full(tree.ngroups, -1, np.int64)
+    c = tree.cells
+    lib().orc_walk(glist.shape[0], glist, tree.gbeg, tree.gcnt, _f32(tree.gc.reshape(-1)),
+                   _f32(tree.gh.reshape(-1)), c["ncell"], c["begin"], c["count"], c["child0"],
+                   c["nchild"], tree.mom["M"], _f64(tree.mom["com"].reshape(-1)),
+                   _f64(tree.mom["Q"].reshape(-1)), _f32(tree.mom["comf"].reshape(-1)), ro2,
+                   tree.x, tree.y, tree.z, tree.m, float(eps), acc_s, pot_s, npp, npc, ncov,
+                   nself)
+    acc = np.full((n, 3), np.nan)
+    pot = np.full(n, np.nan)
+    acc[tree.perm] = acc_s.reshape(n, 3)
+    pot[tree.perm] = pot_s
+    if diag:
+        return acc, pot, npp, npc, ncov, nself
+    return acc, pot, npp, npc
+
+
+def tree_force(pos, mass, theta, eps, nleaf=NLEAF, ncrit=NCRIT):
+    t = build_tree(pos, mass, nleaf, ncrit)
+    acc, pot, npp, npc = walk(t, theta, eps)
+    return acc, pot, t, npp, npc
+
+
+def direct(pos, mass, eps, targets=None):
+    """Direct-summation accelerations and potentials (FP64) at the targets."""
+    pos = _f64(pos).reshape(-1, 3)
+    mass = _f64(mass).reshape(-1)
+    n = pos.shape[0]
+    tgt = np.arange(n, dtype=np.int64) if targets is None else \
+        np.ascontiguousarray(targets, dtype=np.int64)
+    acc = np.empty(3 * tgt.shape[0])
+    pot = np.empty(tgt.shape[0])
+    lib().orc_direct(n, pos.reshape(-1), mass, tgt.shape[0], tgt, float(eps), acc, pot)
+    return acc.reshape(-1, 3), pot
+
+
+def expansion(targets, mc, comc, qc, eps=0.0):
+    """Eq. (1)/(2) of a single cell (mass, centre, quadrupole xx,yy,zz,xy,xz,yz)."""
+    t = _f64(targets).reshape(-1, 3)
+    acc = np.empty(3 * t.shape[0])
+    pot = np.empty(t.shape[0])
+    lib().orc_expansion(t.shape[0], t.reshape(-1), float(mc), _f64(comc), _f64(qc), float(eps),
+                        acc, pot)
+    return acc.reshape(-1, 3), pot
+
+
+# --- O10: second-order leapfrog (kick-drift-kick) --------------------------------
+
+def leapfrog(pos, vel, mass, dt, steps, force):
+    """KDK leapfrog in FP64 with a shared time step.
+
+    ``force(pos64) -> acc64`` gives the accelerations; the force at the
+    initial positions is computed first.  Returns (pos, vel) after ``steps``.
+    """
+    x = _f64(pos).reshape(-1, 3).copy()
+    v = _f64(vel).reshape(-1, 3).copy()
+    a = force(x)
+    for _ in range(steps):
+        v = v + 0.5 * dt * a
+        x = x + dt * v
+        a = force(x)
+        v = v + 0.5 * dt * a
+    return x, v
+
+
+def direct_force_fn(mass, eps):
+    return lambda x: direct(x, mass, eps)[0]
+
+
+def tree_force_fn(mass, theta, eps):
+    """Tree force on positions rounded to FP32 (the tree is defined on FP32)."""
+    return lambda x: tree_force(x.astype(np.float32), mass, theta, eps)[0]
+
+
+def rel_err(a, ref):
+    """Per-target relative error of vectors ||a - ref|| / ||ref||."""
+    a = np.asarray(a, np.float64)
+    ref = np.asarray(ref, np.float64)
+    if a.ndim == 1:
+        return np.abs(a - ref) / np.abs(ref)
+    return np.sqrt(((a - ref) ** 2).sum(1)) / np.sqrt((ref ** 2).sum(1))
