@@ -1,0 +1,184 @@
+"""Benchmark: one leapfrog step of the tree-code per step (sort, build,
+moments, walk + force, kicks and drift) on one MI355X.
+
+Prints one JSON line.  `value` is tree-walk interactions (particle-particle +
+particle-cell) per second of whole-step wall time; the walk kernel's own
+rate and its Tflops under the paper's convention (Sec. VI.A: 23 flops per
+particle-particle and 65 per particle-cell interaction) are reported beside
+it, with the walk's fraction of the FP32 vector peak.  The CPU baseline is
+the oracle (FP64 C tree code) timed on a bounded sample of the same
+workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FLOPS_PP = 23
+FLOPS_PC = 65
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CUs x 2.4 GHz x 256 flop/clk)
+WALK_SOURCE = os.path.join(ROOT, "paper_1412_0659_amd", "csrc", "walk.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_disk_halo_13m_traffic.json")
+
+
+def paper_flops(n_pp, n_pc):
+    """Flops of a walk under the paper's convention (Sec. VI.A)."""
+    return FLOPS_PP * float(n_pp) + FLOPS_PC * float(n_pc)
+
+
+def walk_source_hash():
+    with open(WALK_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per walk launch from the committed rocprofv3 counter summary,
+    or None if absent or taken on a different walk kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("walk_source_sha256_16") != walk_source_hash():
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(snap, theta, eps, budget_s=12.0):
+    """Time the oracle's tree walk over a seeded sample of groups."""
+    import numpy as np
+
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    tree = O.build_tree(snap.pos, snap.mass)
+    t_build = time.perf_counter() - t0
+    rng = np.random.default_rng(1234)
+    order = rng.permutation(tree.ngroups)
+    done, inter, walk_s, k = 0, 0, 0.0, 64
+    while done < len(order) and walk_s < budget_s:
+        sel = order[done:done + k]
+        t1 = time.perf_counter()
+        _, _, npp, npc = O.walk(tree, theta, eps, groups=sel)
+        walk_s += time.perf_counter() - t1
+        inter += int(((npp[sel] + npc[sel]) * tree.gcnt[sel]).sum())
+        done += len(sel)
+        k = min(4 * k, 4096)
+    targets = int(tree.gcnt[order[:done]].sum())
+    return {
+        "value": inter / walk_s, "unit": "interactions/s", "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle walk of {done} random groups ({targets} targets) of the "
+                   f"{tree.n}-particle tree, theta={theta}, eps={eps}; {walk_s:.1f} s of walk; "
+                   f"oracle tree build over all particles took {t_build:.1f} s (not in value)"),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="disk_halo_13m")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is not part of this build)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1412_0659_amd as bh
+    from workloads import ics
+
+    w = ics.WORKLOADS[args.workload]
+    theta, eps, dt = w["theta"], w["eps"], w.get("dt", 1e-3)
+    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    t0 = time.perf_counter()
+    snap = ics.make(args.workload)
+    log(f"[bench] workload {args.workload} n={snap.n} generated in {time.perf_counter() - t0:.1f} s")
+
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(snap.pos).to(dev)
+    vel = torch.from_numpy(snap.vel).to(dev)
+    mass = torch.from_numpy(snap.mass).to(dev)
+    tree = bh.Tree(snap.n)
+    tree.set_state(pos, vel, mass)
+    tree.sync()
+    for k in range(args.warmup):
+        tree.step(dt, theta, eps)
+        tree.sync()
+        log(f"[bench] warmup step {k} done")
+
+    torch.cuda.synchronize()
+    per = []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        tree.step(dt, theta, eps)
+        per.append(tree.stats())       # synchronises the stream
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    log(f"[bench] {args.steps} timed steps in {wall:.3f} s")
+
+    n_pp = sum(s["n_pp"] for s in per)
+    n_pc = sum(s["n_pc"] for s in per)
+    walk_ms = sum(s["ms_walk"] for s in per)
+    inter = n_pp + n_pc
+    flops = paper_flops(n_pp, n_pc)
+    walk_tflops = flops / (walk_ms * 1e-3) / 1e12
+    last = per[-1]
+    out = {
+        "metric": "tree-walk interactions/s & Tflops at N=13M, θ=0.4; FP16-far vs FP32 at force err",
+        "value": inter / wall,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": snap.n, "theta": theta, "eps": eps, "dt": dt,
+                   "nleaf": 16, "ncrit": 64, "model": "exponential disk + Hernquist halo"
+                   if w["model"] == "disk_halo" else "Plummer sphere"},
+        "tflops_step": flops / wall / 1e12,
+        "tflops_walk": walk_tflops,
+        "interactions_per_s_walk": inter / (walk_ms * 1e-3),
+        "pp_per_particle": n_pp / args.steps / snap.n,
+        "pc_per_particle": n_pc / args.steps / snap.n,
+        "ms_phase": {"sort": np.mean([s["ms_sort"] for s in per]),
+                     "build": np.mean([s["ms_build"] for s in per]),
+                     "moments": np.mean([s["ms_moments"] for s in per]),
+                     "walk": walk_ms / args.steps,
+                     "step_events": np.mean([s["ms_step"] for s in per])},
+        "tree": {"cells": last["ncells"], "leaves": last["nleaves"], "groups": last["ngroups"],
+                 "depth": last["depth"]},
+        "roofline": {"bound": "alu", "achieved": walk_tflops, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": walk_tflops / PEAK_FP32_TFLOPS,
+                     "traffic": load_traffic(), "kernel": "k_walk",
+                     "flops_convention": "23 per p-p, 65 per p-c (paper Sec. VI.A)"},
+    }
+    tree.close()
+    if not args.no_cpu_baseline:
+        log("[bench] CPU baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(snap, theta, eps)
+    out["ms_phase"] = {k: float(v) for k, v in out["ms_phase"].items()}
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,184 @@
+/*
+ * bh.h -- C ABI of the MI355X (gfx950) Barnes-Hut tree-code library.
+ *
+ * The library computes one gravitational force evaluation and one
+ * leapfrog step of a particle system on one GPU, following the tree-code of
+ * Bedorf et al., "24.77 Pflops on a Gravitational Tree-Code to Simulate the
+ * Milky Way Galaxy with 18600 GPUs" (SC14):
+ *
+ *   tree_build     bounding box, space-filling-curve keys and key sort
+ *                  (Sec. III.B.1; Table II "Sorting SFC"), octree
+ *                  construction with at most 16 particles per leaf (Sec. I.A;
+ *                  Table II "Tree-construction"), target groups, and the
+ *                  multipole moments of every cell (Sec. I.A; Table II
+ *                  "Tree-properties")
+ *   tree_force     the group-wise tree walk with opening angle theta, fused
+ *                  with the force evaluation of Sec. VI.A Eq. (1)-(2)
+ *                  (Sec. III.A; Table II "Compute gravity")
+ *   leapfrog_step  one second-order kick-drift-kick leapfrog step with a full
+ *                  tree rebuild (Sec. III.B.2)
+ *
+ * Conventions for every entry point:
+ *   - G = 1.  Positions are [N][3] row-major FP32, masses [N] FP32 (> 0).
+ *   - "device" pointers are HIP device allocations on the context's device;
+ *     "host" pointers are ordinary host memory.
+ *   - Work is enqueued on the caller's HIP stream `s` (0 = the null stream)
+ *     and runs asynchronously unless the entry point says it synchronises.
+ *     A context must be used from one host thread and one stream at a time;
+ *     the library takes no locks.
+ *   - Every call returns BH_OK (0) or a negative bh_status; nothing aborts
+ *     or throws across the ABI.  bh_last_error() describes the last failure.
+ *   - Conditions found on the device (a non-finite position or a
+ *     non-positive mass at build time) are latched in a device status word
+ *     and reported by the next synchronising call (bh_sync, bh_stats,
+ *     bh_export, bh_get_state).
+ */
+#ifndef BH_H
+#define BH_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bh_status {
+    BH_OK = 0,
+    BH_EINVAL = -1,      /* an argument is out of range (n <= 0, theta outside
+                            (0, 1], eps < 0 or not finite, dt not finite,
+                            null pointer, unknown export id) */
+    BH_ECAPACITY = -2,   /* n > n_max of the context, or an export buffer is
+                            too small */
+    BH_ENOMEM = -3,      /* device allocation failed in bh_create */
+    BH_EHIP = -4,        /* a HIP runtime call failed */
+    BH_ENONFINITE = -5,  /* device status: non-finite position or velocity */
+    BH_ESTATE = -6,      /* call out of order (force or step before a build) */
+    BH_EMASS = -7        /* device status: a mass is <= 0 or not finite */
+} bh_status;
+
+/* Tree parameters, fixed for the lifetime of a context. */
+typedef struct bh_params {
+    int32_t nleaf;    /* a cell holding more than nleaf particles is split
+                         (Sec. I.A uses 16); 1..64 */
+    int32_t ncrit;    /* target groups hold at most ncrit particles; 1..64 */
+    int32_t far_fp16; /* reserved, must be 0 */
+    int32_t pos_fp64; /* reserved, must be 0 */
+    int32_t reserved[4];
+} bh_params;
+
+typedef struct bh_ctx bh_ctx;
+
+/* Create a context on the current HIP device with room for up to n_max
+ * particles.  The context owns every buffer the path needs (sorted particle
+ * state, keys, cells, moments, groups); they are allocated here, once.
+ * p == NULL selects nleaf = 16, ncrit = 64.  On success *out is set. */
+int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p);
+
+/* Free the context and all its device memory (synchronises the device). */
+int bh_destroy(bh_ctx *ctx);
+
+/* Build the tree for n particles (Sec. III.B.1, Sec. I.A).
+ *   pos   device, [n][3] FP32, caller order
+ *   mass  device, [n] FP32, caller order, every mass > 0
+ * The particle state becomes (pos, velocity 0, mass).  The inputs are read
+ * by work enqueued on s; the caller may reuse them once s has passed that
+ * point.  Errors: BH_EINVAL (n <= 0, null pointer), BH_ECAPACITY
+ * (n > n_max); non-finite positions / bad masses are latched. */
+int tree_build(bh_ctx *ctx, const float *pos, const float *mass, int64_t n, hipStream_t s);
+
+/* Set positions, velocities and masses (device, caller order; vel may be
+ * NULL for zero velocities) and build the tree for them.  Same errors as
+ * tree_build. */
+int bh_set_state(bh_ctx *ctx, const float *pos, const float *vel, const float *mass, int64_t n,
+                 hipStream_t s);
+
+/* Forces on every particle from the last built tree (Sec. III.A, Sec. VI.A
+ * Eq. (1)-(2) with Plummer softening eps).
+ *   theta  opening angle, 0 < theta <= 1
+ *   eps    softening length >= 0
+ *   acc    device, [n][3] FP32, caller order (may be NULL)
+ *   pot    device, [n] FP32, caller order (may be NULL); the self pair is
+ *          excluded from the potential
+ * The outputs are valid once s has passed this work.  Errors: BH_EINVAL,
+ * BH_ESTATE (no tree built). */
+int tree_force(bh_ctx *ctx, float theta, float eps, float *acc, float *pot, hipStream_t s);
+
+/* One kick-drift-kick step (Sec. III.B.2): v += a dt/2; x += v dt; rebuild
+ * the tree; a = force(x); v += a dt/2.  The force at the current state is
+ * computed first when the last call did not leave one for (theta, eps).
+ * Errors: BH_EINVAL (dt not finite, theta/eps out of range), BH_ESTATE. */
+int leapfrog_step(bh_ctx *ctx, float dt, float theta, float eps, hipStream_t s);
+
+/* Copy the particle state out in caller order (device pointers, [n][3];
+ * either may be NULL).  Synchronises s and reports latched device status. */
+int bh_get_state(bh_ctx *ctx, float *pos, float *vel, hipStream_t s);
+
+/* Wait for s and return the latched device status (BH_OK if clean). */
+int bh_sync(bh_ctx *ctx, hipStream_t s);
+
+typedef struct bh_stats {
+    int64_t n;            /* particles of the current state */
+    int64_t ncells;       /* cells of the last built tree */
+    int64_t nleaves;      /* leaf cells */
+    int64_t ngroups;      /* target groups */
+    int64_t depth;        /* deepest level holding a cell */
+    int64_t n_pp;         /* particle-particle interactions of the last walk
+                             (sum over groups of npp * group size) */
+    int64_t n_pc;         /* particle-cell interactions of the last walk */
+    double ms_sort;       /* bounding box + keys + sort + gather of the last build */
+    double ms_build;      /* octree + groups of the last build */
+    double ms_moments;    /* moment pass of the last build */
+    double ms_walk;       /* walk kernel of the last force evaluation */
+    double ms_step;       /* whole last leapfrog_step (0 if none) */
+} bh_stats;
+
+/* Fill *out (host).  Synchronises s and reports latched device status. */
+int bh_stats_get(bh_ctx *ctx, bh_stats *out, hipStream_t s);
+
+/* Arrays that bh_export can copy out, with element type and count. */
+typedef enum bh_array {
+    BH_ARR_KEYS = 1,        /* u64 [n]      sorted Morton keys */
+    BH_ARR_PERM = 2,        /* u32 [n]      sorted slot -> caller index */
+    BH_ARR_BOX = 3,         /* f32 [5]      lo x, y, z, side, scale */
+    BH_ARR_LEVEL_START = 4, /* u32 [23]     first cell of each level; [22] = ncells */
+    BH_ARR_CELL_LEVEL = 5,  /* u32 [ncells] */
+    BH_ARR_CELL_PREFIX = 6, /* u64 [ncells] key >> 3 (21 - level) of the cell */
+    BH_ARR_CELL_BEGIN = 7,  /* u32 [ncells] first sorted particle */
+    BH_ARR_CELL_COUNT = 8,  /* u32 [ncells] */
+    BH_ARR_CELL_CHILD0 = 9, /* u32 [ncells] first child (undefined for leaves) */
+    BH_ARR_CELL_NCHILD = 10,/* u32 [ncells] 0 for leaves */
+    BH_ARR_CELL_PARENT = 11,/* u32 [ncells] 0xffffffff for the root */
+    BH_ARR_MOM_M = 12,      /* f64 [ncells] mass */
+    BH_ARR_MOM_COM = 13,    /* f64 [ncells][3] centre of mass */
+    BH_ARR_MOM_Q = 14,      /* f64 [ncells][6] quadrupole xx, yy, zz, xy, xz, yz */
+    BH_ARR_CELL_COMF = 15,  /* f32 [ncells][4] centre of mass (FP32), r_open^2 of
+                               the last force evaluation */
+    BH_ARR_CELL_SIZE = 16,  /* f32 [ncells][2] cell size l, |com - centre| */
+    BH_ARR_GROUP_BEGIN = 17,/* u32 [ngroups] */
+    BH_ARR_GROUP_COUNT = 18,/* u32 [ngroups] */
+    BH_ARR_GROUP_BOX = 19,  /* f32 [ngroups][8] centre xyz, 0, half size xyz, 0
+                               (written by the walk) */
+    BH_ARR_GROUP_NPP = 20,  /* u32 [ngroups] particle-particle sources of the last walk */
+    BH_ARR_GROUP_NPC = 21,  /* u32 [ngroups] particle-cell sources of the last walk */
+    BH_ARR_ACC_SORTED = 22  /* f32 [n][4] ax, ay, az, potential in sorted order */
+} bh_array;
+
+/* Copy one array of the last build / walk to host memory `dst` (capacity
+ * `cap_bytes`); *nbytes (may be NULL) receives the byte count.  Synchronises
+ * s.  Errors: BH_EINVAL (unknown id), BH_ECAPACITY (dst too small),
+ * BH_ESTATE (nothing built). */
+int bh_export(bh_ctx *ctx, int array, void *dst, int64_t cap_bytes, int64_t *nbytes,
+              hipStream_t s);
+
+/* Static description of a status code. */
+const char *bh_strerror(int status);
+
+/* Description of the last failure on this context ("" if none). */
+const char *bh_last_error(const bh_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BH_H */

@@ -1,0 +1,245 @@
+"""ctypes binding of the C ABI in include/bh.h.
+
+Argument marshalling only: every step of the tree-code runs in the HIP
+library libbh.so next to this file.  The entry points keep the C names
+(bh_create, tree_build, tree_force, leapfrog_step, ...); torch supplies the
+device memory (``tensor.data_ptr()``) and the stream
+(``torch.cuda.current_stream().cuda_stream``).  There is no fallback: if the
+library is missing, loading fails with an error that says how to build it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbh.so")
+
+BH_OK, BH_EINVAL, BH_ECAPACITY, BH_ENOMEM, BH_EHIP, BH_ENONFINITE, BH_ESTATE, BH_EMASS = \
+    0, -1, -2, -3, -4, -5, -6, -7
+
+# export id -> (numpy dtype, values per element, element count kind)
+EXPORTS = {
+    "keys": (1, np.uint64, 1), "perm": (2, np.uint32, 1), "box": (3, np.float32, 1),
+    "level_start": (4, np.uint32, 1), "cell_level": (5, np.uint32, 1),
+    "cell_prefix": (6, np.uint64, 1), "cell_begin": (7, np.uint32, 1),
+    "cell_count": (8, np.uint32, 1), "cell_child0": (9, np.uint32, 1),
+    "cell_nchild": (10, np.uint32, 1), "cell_parent": (11, np.uint32, 1),
+    "mom_M": (12, np.float64, 1), "mom_com": (13, np.float64, 3), "mom_Q": (14, np.float64, 6),
+    "cell_comf": (15, np.float32, 4), "cell_size": (16, np.float32, 2),
+    "group_begin": (17, np.uint32, 1), "group_count": (18, np.uint32, 1),
+    "group_box": (19, np.float32, 8), "group_npp": (20, np.uint32, 1),
+    "group_npc": (21, np.uint32, 1), "acc_sorted": (22, np.float32, 4),
+}
+
+
+class BhError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class bh_params(ctypes.Structure):
+    _fields_ = [("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32),
+                ("far_fp16", ctypes.c_int32), ("pos_fp64", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class bh_stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ncells", ctypes.c_int64), ("nleaves", ctypes.c_int64),
+                ("ngroups", ctypes.c_int64), ("depth", ctypes.c_int64), ("n_pp", ctypes.c_int64),
+                ("n_pc", ctypes.c_int64), ("ms_sort", ctypes.c_double),
+                ("ms_build", ctypes.c_double), ("ms_moments", ctypes.c_double),
+                ("ms_walk", ctypes.c_double), ("ms_step", ctypes.c_double)]
+
+
+SYMBOLS = ["bh_create", "bh_destroy", "tree_build", "bh_set_state", "tree_force",
+           "leapfrog_step", "bh_get_state", "bh_sync", "bh_stats_get", "bh_export",
+           "bh_strerror", "bh_last_error"]
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def load():
+    """Load libbh.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                           "(run `python -c 'import __graft_entry__ as g; g.build()'`)")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, f32, c_int = ctypes.c_int64, ctypes.c_float, ctypes.c_int
+    sig = {
+        "bh_create": ([ctypes.POINTER(_vp), i64, ctypes.POINTER(bh_params)], c_int),
+        "bh_destroy": ([_vp], c_int),
+        "tree_build": ([_vp, _vp, _vp, i64, _vp], c_int),
+        "bh_set_state": ([_vp, _vp, _vp, _vp, i64, _vp], c_int),
+        "tree_force": ([_vp, f32, f32, _vp, _vp, _vp], c_int),
+        "leapfrog_step": ([_vp, f32, f32, f32, _vp], c_int),
+        "bh_get_state": ([_vp, _vp, _vp, _vp], c_int),
+        "bh_sync": ([_vp, _vp], c_int),
+        "bh_stats_get": ([_vp, ctypes.POINTER(bh_stats), _vp], c_int),
+        "bh_export": ([_vp, c_int, _vp, i64, ctypes.POINTER(i64), _vp], c_int),
+        "bh_strerror": ([c_int], ctypes.c_char_p),
+        "bh_last_error": ([_vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(ctx, rc):
+    if rc != BH_OK:
+        L = load()
+        msg = (L.bh_last_error(ctx) or b"").decode() if ctx else ""
+        if not msg:
+            msg = L.bh_strerror(rc).decode()
+        raise BhError(rc, msg)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()
+            and t.dtype == torch.float32):
+        raise TypeError("expected a contiguous float32 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# --- the C entry points, same names ------------------------------------------
+
+def bh_create(n_max: int, nleaf: int = 16, ncrit: int = 64):
+    p = bh_params(nleaf, ncrit, 0, 0)
+    out = _vp()
+    rc = load().bh_create(ctypes.byref(out), int(n_max), ctypes.byref(p))
+    _check(None, rc)
+    return out
+
+
+def bh_destroy(ctx):
+    _check(None, load().bh_destroy(ctx))
+
+
+def tree_build(ctx, pos, mass, stream=None):
+    n = mass.shape[0]
+    if pos.shape != (n, 3):
+        raise ValueError("pos must be [N, 3]")
+    _check(ctx, load().tree_build(ctx, _ptr(pos), _ptr(mass), n, _stream(stream)))
+
+
+def bh_set_state(ctx, pos, vel, mass, stream=None):
+    n = mass.shape[0]
+    if pos.shape != (n, 3) or (vel is not None and vel.shape != (n, 3)):
+        raise ValueError("pos and vel must be [N, 3]")
+    _check(ctx, load().bh_set_state(ctx, _ptr(pos), _ptr(vel), _ptr(mass), n, _stream(stream)))
+
+
+def tree_force(ctx, theta, eps, acc=None, pot=None, stream=None):
+    _check(ctx, load().tree_force(ctx, float(theta), float(eps), _ptr(acc), _ptr(pot),
+                                  _stream(stream)))
+
+
+def leapfrog_step(ctx, dt, theta, eps, stream=None):
+    _check(ctx, load().leapfrog_step(ctx, float(dt), float(theta), float(eps), _stream(stream)))
+
+
+def bh_get_state(ctx, pos=None, vel=None, stream=None):
+    _check(ctx, load().bh_get_state(ctx, _ptr(pos), _ptr(vel), _stream(stream)))
+
+
+def bh_sync(ctx, stream=None):
+    _check(ctx, load().bh_sync(ctx, _stream(stream)))
+
+
+def bh_stats_get(ctx, stream=None) -> dict:
+    st = bh_stats()
+    _check(ctx, load().bh_stats_get(ctx, ctypes.byref(st), _stream(stream)))
+    return {k: getattr(st, k) for k, _ in bh_stats._fields_}
+
+
+def bh_export(ctx, name: str, count: int, stream=None) -> np.ndarray:
+    aid, dt, width = EXPORTS[name]
+    out = np.empty(count * width, dtype=dt)
+    nb = ctypes.c_int64(0)
+    _check(ctx, load().bh_export(ctx, aid, out.ctypes.data_as(_vp), out.nbytes, ctypes.byref(nb),
+                                 _stream(stream)))
+    k = nb.value // np.dtype(dt).itemsize
+    out = out[:k]
+    return out.reshape(-1, width) if width > 1 else out
+
+
+class Tree:
+    """Owns one library context; methods call the C entry points."""
+
+    def __init__(self, n_max: int, nleaf: int = 16, ncrit: int = 64):
+        self.ctx = bh_create(n_max, nleaf, ncrit)
+        self.n = 0
+
+    def close(self):
+        if self.ctx:
+            bh_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build(self, pos, mass):
+        tree_build(self.ctx, pos, mass)
+        self.n = mass.shape[0]
+
+    def set_state(self, pos, vel, mass):
+        bh_set_state(self.ctx, pos, vel, mass)
+        self.n = mass.shape[0]
+
+    def force(self, theta, eps, acc=None, pot=None):
+        import torch
+        if acc is None:
+            acc = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
+        if pot is None:
+            pot = torch.empty((self.n,), dtype=torch.float32, device="cuda")
+        tree_force(self.ctx, theta, eps, acc, pot)
+        return acc, pot
+
+    def step(self, dt, theta, eps):
+        leapfrog_step(self.ctx, dt, theta, eps)
+
+    def state(self):
+        import torch
+        pos = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
+        vel = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
+        bh_get_state(self.ctx, pos, vel)
+        return pos, vel
+
+    def sync(self):
+        bh_sync(self.ctx)
+
+    def stats(self) -> dict:
+        return bh_stats_get(self.ctx)
+
+    def export(self, name: str) -> np.ndarray:
+        st = self.stats()
+        sizes = {"keys": st["n"], "perm": st["n"], "acc_sorted": st["n"], "box": 5,
+                 "level_start": 23}
+        if name.startswith("cell") or name.startswith("mom"):
+            count = st["ncells"]
+        elif name.startswith("group"):
+            count = st["ngroups"]
+        else:
+            count = sizes[name]
+        return bh_export(self.ctx, name, count)

@@ -1,0 +1,374 @@
+// C ABI of the tree-code library: context, argument checks, the order of the
+// launches for a build / force evaluation / leapfrog step, statistics and
+// array export.  Declarations and contracts are in include/bh.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "bh_internal.h"
+
+using namespace bh;
+
+namespace {
+
+int fail(bh_ctx *c, int code, const std::string &msg) {
+    if (c) c->last_error = msg;
+    return code;
+}
+
+#define BH_HIP(ctx, call)                                                                 \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail((ctx), BH_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+bool dalloc(T **p, size_t count, std::string &err) {
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * std::max<size_t>(count, 1));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        err = std::string("hipMalloc: ") + hipGetErrorString(e);
+        (void)hipGetLastError();
+        return false;
+    }
+    return true;
+}
+
+void free_all(bh_ctx *c) {
+    auto f = [](void *p) {
+        if (p) (void)hipFree(p);
+    };
+    for (int k = 0; k < 2; ++k) {
+        State &s = c->st[k];
+        f(s.x); f(s.y); f(s.z); f(s.m); f(s.vx); f(s.vy); f(s.vz); f(s.cid);
+        f(c->sort.key[k]); f(c->sort.idx[k]);
+    }
+    f(c->acc); f(c->box); f(c->box_part); f(c->status); f(c->work); f(c->totals);
+    f(c->sort.counts); f(c->sort.scan_part);
+    Cells &q = c->cells;
+    f(q.prefix); f(q.level); f(q.begin); f(q.count); f(q.child0); f(q.nchild); f(q.parent);
+    f(q.ls); f(q.part); f(q.M); f(q.S); f(q.com); f(q.Q); f(q.wA); f(q.wM); f(q.wQ); f(q.wN);
+    f(q.size); f(q.trm);
+    Groups &g = c->groups;
+    f(g.flag); f(g.scan); f(g.begin); f(g.count_dev); f(g.box); f(g.npp); f(g.npc);
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+}
+
+bool valid_theta(float t) { return std::isfinite(t) && t > 0.f && t <= 1.f; }
+bool valid_eps(float e) { return std::isfinite(e) && e >= 0.f; }
+
+int check_status(bh_ctx *c) {
+    uint32_t st = 0;
+    BH_HIP(c, hipMemcpy(&st, c->status, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (st == 0) return BH_OK;
+    BH_HIP(c, hipMemset(c->status, 0, sizeof(uint32_t)));
+    if (st & kStNonFinite) return fail(c, BH_ENONFINITE, "non-finite position or velocity");
+    if (st & kStMass) return fail(c, BH_EMASS, "mass <= 0 or not finite");
+    return fail(c, BH_ECAPACITY, "cell or stack capacity exceeded");
+}
+
+void rebuild(bh_ctx *c, uint32_t n, hipStream_t s) {
+    hipEventRecord(c->ev[0], s);
+    launch_bbox(c, c->st[c->cur], n, s);
+    launch_keys(c, c->st[c->cur], n, s);
+    launch_radix_sort(c, n, s);
+    launch_gather(c, n, s);
+    hipEventRecord(c->ev[1], s);
+    launch_build(c, n, s);
+    launch_groups(c, n, s);
+    hipEventRecord(c->ev[2], s);
+    launch_moments(c, s);
+    hipEventRecord(c->ev[3], s);
+    c->ev_rec[0] = c->ev_rec[1] = c->ev_rec[2] = c->ev_rec[3] = true;
+    c->built = true;
+    c->have_acc = false;
+}
+
+void force(bh_ctx *c, float theta, float eps, hipStream_t s) {
+    launch_walk_prep(c, theta, s);
+    launch_walk(c, eps, s);
+    launch_totals(c, (uint32_t)c->n, s);
+    c->have_acc = true;
+    c->acc_theta = theta;
+    c->acc_eps = eps;
+}
+
+int check_n(bh_ctx *c, int64_t n) {
+    if (n <= 0) return fail(c, BH_EINVAL, "n must be positive");
+    if (n > c->nmax) return fail(c, BH_ECAPACITY, "n exceeds the context capacity");
+    return BH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bh_strerror(int status) {
+    switch (status) {
+        case BH_OK: return "ok";
+        case BH_EINVAL: return "invalid argument";
+        case BH_ECAPACITY: return "capacity exceeded";
+        case BH_ENOMEM: return "device allocation failed";
+        case BH_EHIP: return "HIP runtime error";
+        case BH_ENONFINITE: return "non-finite particle data";
+        case BH_ESTATE: return "call out of order";
+        case BH_EMASS: return "non-positive mass";
+        default: return "unknown status";
+    }
+}
+
+const char *bh_last_error(const bh_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
+    if (!out) return BH_EINVAL;
+    *out = nullptr;
+    bh_params prm{};
+    prm.nleaf = 16;
+    prm.ncrit = 64;
+    if (p) prm = *p;
+    if (n_max <= 0 || prm.nleaf < 1 || prm.nleaf > 64 || prm.ncrit < 1 || prm.ncrit > 64 ||
+        prm.far_fp16 != 0 || prm.pos_fp64 != 0)
+        return BH_EINVAL;
+    // cells: <= n leaves + 21 levels x n / (nleaf + 1) internal cells; the walk
+    // packs a cell index into 29 bits
+    int64_t cap = n_max + 21 * (n_max / (prm.nleaf + 1)) + 1;
+    if (cap >= (int64_t(1) << 29)) return BH_EINVAL;
+
+    bh_ctx *c = new (std::nothrow) bh_ctx();
+    if (!c) return BH_ENOMEM;
+    c->nmax = n_max;
+    c->cap_cells = cap;
+    c->p = prm;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return BH_EHIP;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
+        delete c;
+        return BH_EHIP;
+    }
+    c->cus = prop.multiProcessorCount;
+
+    std::string err;
+    bool ok = true;
+    size_t n = (size_t)n_max, nc = (size_t)cap;
+    for (int k = 0; k < 2 && ok; ++k) {
+        State &s = c->st[k];
+        ok = dalloc(&s.x, n, err) && dalloc(&s.y, n, err) && dalloc(&s.z, n, err) &&
+             dalloc(&s.m, n, err) && dalloc(&s.vx, n, err) && dalloc(&s.vy, n, err) &&
+             dalloc(&s.vz, n, err) && dalloc(&s.cid, n, err) && dalloc(&c->sort.key[k], n, err) &&
+             dalloc(&c->sort.idx[k], n, err);
+    }
+    c->sort.counts_len = sort_counts_len(n_max);
+    c->sort.scan_part_len = std::max(scan_part_len(c->sort.counts_len), scan_part_len(n_max));
+    Cells &q = c->cells;
+    Groups &g = c->groups;
+    ok = ok && dalloc(&c->acc, n, err) && dalloc(&c->box, 8, err) &&
+         dalloc(&c->box_part, 6 * 1024, err) && dalloc(&c->status, 4, err) &&
+         dalloc(&c->work, 8, err) && dalloc(&c->totals, 2, err) &&
+         dalloc(&c->sort.counts, (size_t)c->sort.counts_len, err) &&
+         dalloc(&c->sort.scan_part, (size_t)c->sort.scan_part_len, err) &&
+         dalloc(&q.prefix, nc, err) && dalloc(&q.level, nc, err) && dalloc(&q.begin, nc, err) &&
+         dalloc(&q.count, nc, err) && dalloc(&q.child0, nc, err) && dalloc(&q.nchild, nc, err) &&
+         dalloc(&q.parent, nc, err) && dalloc(&q.ls, kLsSize, err) &&
+         dalloc(&q.part, kGrid + 1, err) && dalloc(&q.M, nc, err) && dalloc(&q.S, 3 * nc, err) &&
+         dalloc(&q.com, 3 * nc, err) && dalloc(&q.Q, 6 * nc, err) && dalloc(&q.wA, nc, err) &&
+         dalloc(&q.wM, nc, err) && dalloc(&q.wQ, nc, err) && dalloc(&q.wN, nc, err) &&
+         dalloc(&q.size, nc, err) && dalloc(&q.trm, nc, err) && dalloc(&g.flag, n, err) &&
+         dalloc(&g.scan, n, err) && dalloc(&g.begin, n + 1, err) &&
+         dalloc(&g.count_dev, 1, err) && dalloc(&g.box, 2 * n, err) && dalloc(&g.npp, n, err) &&
+         dalloc(&g.npc, n, err);
+    for (auto &e : c->ev)
+        if (ok && hipEventCreate(&e) != hipSuccess) ok = false;
+    if (ok && hipMemset(c->status, 0, 4 * sizeof(uint32_t)) != hipSuccess) ok = false;
+    if (!ok) {
+        free_all(c);
+        delete c;
+        return BH_ENOMEM;
+    }
+    c->walk_grid = std::max(1, c->cus) * walk_blocks_per_cu();
+    *out = c;
+    return BH_OK;
+}
+
+int bh_destroy(bh_ctx *c) {
+    if (!c) return BH_EINVAL;
+    (void)hipDeviceSynchronize();
+    free_all(c);
+    delete c;
+    return BH_OK;
+}
+
+int tree_build(bh_ctx *c, const float *pos, const float *mass, int64_t n, hipStream_t s) {
+    return bh_set_state(c, pos, nullptr, mass, n, s);
+}
+
+int bh_set_state(bh_ctx *c, const float *pos, const float *vel, const float *mass, int64_t n,
+                 hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!pos || !mass) return fail(c, BH_EINVAL, "null pointer");
+    int rc = check_n(c, n);
+    if (rc) return rc;
+    c->n = n;
+    c->cur = 0;
+    launch_ingest(c, pos, vel, mass, (uint32_t)n, s);
+    rebuild(c, (uint32_t)n, s);
+    c->ev_rec[6] = c->ev_rec[7] = false;
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+int tree_force(bh_ctx *c, float theta, float eps, float *acc, float *pot, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!valid_theta(theta)) return fail(c, BH_EINVAL, "theta must be in (0, 1]");
+    if (!valid_eps(eps)) return fail(c, BH_EINVAL, "eps must be finite and >= 0");
+    if (!c->built) return fail(c, BH_ESTATE, "tree_force before tree_build");
+    force(c, theta, eps, s);
+    if (acc || pot) launch_unsort(c, acc, pot, (uint32_t)c->n, s);
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+int leapfrog_step(bh_ctx *c, float dt, float theta, float eps, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!std::isfinite(dt)) return fail(c, BH_EINVAL, "dt must be finite");
+    if (!valid_theta(theta)) return fail(c, BH_EINVAL, "theta must be in (0, 1]");
+    if (!valid_eps(eps)) return fail(c, BH_EINVAL, "eps must be finite and >= 0");
+    if (!c->built) return fail(c, BH_ESTATE, "leapfrog_step before tree_build");
+    uint32_t n = (uint32_t)c->n;
+    hipEventRecord(c->ev[6], s);
+    if (!c->have_acc || theta != c->acc_theta || eps != c->acc_eps) force(c, theta, eps, s);
+    launch_kick_drift(c, 0.5f * dt, dt, n, s);
+    rebuild(c, n, s);
+    force(c, theta, eps, s);
+    launch_kick(c, 0.5f * dt, n, s);
+    hipEventRecord(c->ev[7], s);
+    c->ev_rec[6] = c->ev_rec[7] = true;
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+int bh_get_state(bh_ctx *c, float *pos, float *vel, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!c->built) return fail(c, BH_ESTATE, "no state");
+    if (pos || vel) launch_state_out(c, pos, vel, (uint32_t)c->n, s);
+    BH_HIP(c, hipStreamSynchronize(s));
+    return check_status(c);
+}
+
+int bh_sync(bh_ctx *c, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    BH_HIP(c, hipStreamSynchronize(s));
+    return check_status(c);
+}
+
+static double elapsed(bh_ctx *c, int a, int b) {
+    if (!c->ev_rec[a] || !c->ev_rec[b]) return 0.0;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.0;
+    }
+    return ms;
+}
+
+int bh_stats_get(bh_ctx *c, bh_stats *out, hipStream_t s) {
+    if (!c || !out) return BH_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    BH_HIP(c, hipStreamSynchronize(s));
+    out->n = c->n;
+    if (c->built) {
+        uint32_t ls[kLsSize], ng = 0;
+        unsigned long long tot[2] = {0, 0};
+        BH_HIP(c, hipMemcpy(ls, c->cells.ls, sizeof(ls), hipMemcpyDeviceToHost));
+        BH_HIP(c, hipMemcpy(&ng, c->groups.count_dev, sizeof(ng), hipMemcpyDeviceToHost));
+        BH_HIP(c, hipMemcpy(tot, c->totals, sizeof(tot), hipMemcpyDeviceToHost));
+        out->ncells = ls[kLevels];
+        out->ngroups = ng;
+        for (int l = 0; l < kLevels; ++l)
+            if (ls[l + 1] > ls[l]) out->depth = l;
+        if (c->have_acc) {
+            out->n_pp = (int64_t)tot[0];
+            out->n_pc = (int64_t)tot[1];
+        }
+        // leaves: cells with no children
+        uint32_t *nch = new (std::nothrow) uint32_t[out->ncells > 0 ? out->ncells : 1];
+        if (!nch) return fail(c, BH_ENOMEM, "host allocation");
+        hipError_t e = hipMemcpy(nch, c->cells.nchild, sizeof(uint32_t) * out->ncells,
+                                 hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            for (int64_t i = 0; i < out->ncells; ++i) out->nleaves += nch[i] == 0;
+        delete[] nch;
+        BH_HIP(c, e);
+    }
+    out->ms_sort = elapsed(c, 0, 1);
+    out->ms_build = elapsed(c, 1, 2);
+    out->ms_moments = elapsed(c, 2, 3);
+    out->ms_walk = elapsed(c, 4, 5);
+    out->ms_step = elapsed(c, 6, 7);
+    return check_status(c);
+}
+
+int bh_export(bh_ctx *c, int array, void *dst, int64_t cap_bytes, int64_t *nbytes,
+              hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!dst) return fail(c, BH_EINVAL, "null destination");
+    if (!c->built) return fail(c, BH_ESTATE, "nothing built");
+    BH_HIP(c, hipStreamSynchronize(s));
+    uint32_t ls[kLsSize], ng = 0;
+    BH_HIP(c, hipMemcpy(ls, c->cells.ls, sizeof(ls), hipMemcpyDeviceToHost));
+    BH_HIP(c, hipMemcpy(&ng, c->groups.count_dev, sizeof(ng), hipMemcpyDeviceToHost));
+    const size_t n = (size_t)c->n, nc = ls[kLevels];
+    const Cells &q = c->cells;
+    const Groups &g = c->groups;
+    const void *src = nullptr;
+    size_t bytes = 0;
+    switch (array) {
+        case BH_ARR_KEYS: src = c->sort.key[0]; bytes = 8 * n; break;
+        case BH_ARR_PERM: src = c->st[c->cur].cid; bytes = 4 * n; break;
+        case BH_ARR_BOX: src = c->box; bytes = 4 * 5; break;
+        case BH_ARR_LEVEL_START: src = q.ls; bytes = 4 * (kLevels + 1); break;
+        case BH_ARR_CELL_LEVEL: src = q.level; bytes = 4 * nc; break;
+        case BH_ARR_CELL_PREFIX: src = q.prefix; bytes = 8 * nc; break;
+        case BH_ARR_CELL_BEGIN: src = q.begin; bytes = 4 * nc; break;
+        case BH_ARR_CELL_COUNT: src = q.count; bytes = 4 * nc; break;
+        case BH_ARR_CELL_CHILD0: src = q.child0; bytes = 4 * nc; break;
+        case BH_ARR_CELL_NCHILD: src = q.nchild; bytes = 4 * nc; break;
+        case BH_ARR_CELL_PARENT: src = q.parent; bytes = 4 * nc; break;
+        case BH_ARR_MOM_M: src = q.M; bytes = 8 * nc; break;
+        case BH_ARR_MOM_COM: src = q.com; bytes = 24 * nc; break;
+        case BH_ARR_MOM_Q: src = q.Q; bytes = 48 * nc; break;
+        case BH_ARR_CELL_COMF: src = q.wA; bytes = 16 * nc; break;
+        case BH_ARR_CELL_SIZE: src = q.size; bytes = 8 * nc; break;
+        case BH_ARR_GROUP_BEGIN: src = g.begin; bytes = 4 * (size_t)ng; break;
+        case BH_ARR_GROUP_COUNT: {
+            bytes = 4 * (size_t)ng;
+            if ((int64_t)bytes > cap_bytes) return fail(c, BH_ECAPACITY, "export buffer too small");
+            uint32_t *b = new (std::nothrow) uint32_t[(size_t)ng + 1];
+            if (!b) return fail(c, BH_ENOMEM, "host allocation");
+            hipError_t e = hipMemcpy(b, g.begin, 4 * ((size_t)ng + 1), hipMemcpyDeviceToHost);
+            if (e == hipSuccess)
+                for (uint32_t k = 0; k < ng; ++k) ((uint32_t *)dst)[k] = b[k + 1] - b[k];
+            delete[] b;
+            BH_HIP(c, e);
+            if (nbytes) *nbytes = (int64_t)bytes;
+            return check_status(c);
+        }
+        case BH_ARR_GROUP_BOX: src = g.box; bytes = 32 * (size_t)ng; break;
+        case BH_ARR_GROUP_NPP: src = g.npp; bytes = 4 * (size_t)ng; break;
+        case BH_ARR_GROUP_NPC: src = g.npc; bytes = 4 * (size_t)ng; break;
+        case BH_ARR_ACC_SORTED: src = c->acc; bytes = 16 * n; break;
+        default: return fail(c, BH_EINVAL, "unknown export id");
+    }
+    if ((int64_t)bytes > cap_bytes) return fail(c, BH_ECAPACITY, "export buffer too small");
+    if (bytes) BH_HIP(c, hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+    if (nbytes) *nbytes = (int64_t)bytes;
+    return check_status(c);
+}
+
+}  // extern "C"

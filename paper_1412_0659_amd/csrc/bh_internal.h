@@ -1,0 +1,136 @@
+// Internal declarations of the gfx950 tree-code library: the context that
+// owns every device buffer, and the host-side launchers each .hip file
+// provides.  Every kernel is enqueued on the caller's stream; nothing here
+// synchronises except where a launcher says so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "bh.h"
+
+namespace bh {
+
+constexpr int kKeyBits = 21;            // bits per axis of a Morton key
+constexpr int kLevels = 22;             // levels 0..21
+constexpr int kLsSize = 24;             // level_start entries (23 used)
+constexpr int kGrid = 1024;             // fixed grid of the level-wise build kernels
+constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr uint32_t kNone = 0xffffffffu;
+
+// device status word bits
+constexpr uint32_t kStNonFinite = 1u;
+constexpr uint32_t kStMass = 2u;
+constexpr uint32_t kStOverflow = 4u;
+
+// Particle state in sorted (Morton) order, structure of arrays.
+struct State {
+    float *x, *y, *z, *m, *vx, *vy, *vz;
+    uint32_t *cid;  // caller index of each sorted slot
+};
+
+// Octree cells, breadth-first order (level, then key).
+struct Cells {
+    uint64_t *prefix;  // key >> 3 (21 - level)
+    uint32_t *level, *begin, *count, *child0, *nchild, *parent;
+    uint32_t *ls;      // [kLsSize] level_start on the device
+    uint32_t *part;    // [kGrid + 1] per-block partials of the level scans
+    // FP64 moments of the upward pass
+    double *M, *S, *com, *Q;  // [c], [c][3], [c][3], [c][6]
+    // records read by the walk
+    float4 *wA;  // com (FP32) and r_open^2 of the last theta
+    float4 *wM;  // M, Qxx, Qyy, Qzz
+    float4 *wQ;  // Qxy, Qxz, Qyz, trace(Q)/2
+    uint2 *wN;   // internal: (child0, nchild); leaf: (begin, count | kLeafBit)
+    float2 *size;  // cell size l, |com - geometric centre|
+    float *trm;    // -3/2 trace(Q) per cell (second constant of the expansion)
+};
+
+struct Groups {
+    uint32_t *flag, *scan;  // [n] group-start flags and their exclusive scan
+    uint32_t *begin;        // [n + 1]
+    uint32_t *count_dev;    // [1] number of groups
+    float4 *box;            // [2 * n] centre, half size
+    uint32_t *npp, *npc;    // [n]
+};
+
+struct Sort {
+    uint64_t *key[2];
+    uint32_t *idx[2];
+    uint32_t *counts;      // [256 * tiles]
+    uint32_t *scan_part;   // partials of the generic scan
+    int64_t counts_len, scan_part_len;
+};
+
+}  // namespace bh
+
+struct bh_ctx {
+    int64_t nmax = 0, cap_cells = 0, n = 0;
+    bh_params p{};
+    int device = 0;
+    int cus = 0;
+
+    bh::State st[2]{};
+    int cur = 0;
+    float4 *acc = nullptr;  // sorted acceleration + potential
+    float *box = nullptr;   // [8]: lo xyz, side, scale
+    float *box_part = nullptr;
+    uint32_t *status = nullptr;
+    uint32_t *work = nullptr;                // [8] walk work counters
+    unsigned long long *totals = nullptr;    // [2] n_pp, n_pc
+    bh::Sort sort{};
+    bh::Cells cells{};
+    bh::Groups groups{};
+
+    bool built = false, have_acc = false;
+    float acc_theta = 0.f, acc_eps = 0.f;
+    int walk_grid = 0;
+
+    // events: build start, after sort, after octree+groups, after moments,
+    // walk start, walk end, step start, step end
+    hipEvent_t ev[8]{};
+    bool ev_rec[8]{};
+    std::string last_error;
+};
+
+namespace bh {
+
+// keys_sort.hip
+void launch_bbox(bh_ctx *c, const State &s, uint32_t n, hipStream_t st);
+void launch_keys(bh_ctx *c, const State &s, uint32_t n, hipStream_t st);
+void launch_radix_sort(bh_ctx *c, uint32_t n, hipStream_t st);  // result in key[0], idx[0]
+void launch_gather(bh_ctx *c, uint32_t n, hipStream_t st);      // st[cur] -> st[cur ^ 1]
+int64_t sort_counts_len(int64_t nmax);
+int64_t scan_part_len(int64_t n);
+
+// scan.hip: exclusive scan of n u32 (in may equal out); part >= scan_part_len(n)
+void launch_exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *part,
+                           hipStream_t st);
+
+// build.hip
+void launch_build(bh_ctx *c, uint32_t n, hipStream_t st);
+void launch_groups(bh_ctx *c, uint32_t n, hipStream_t st);
+
+// moments.hip
+void launch_moments(bh_ctx *c, hipStream_t st);
+void launch_walk_prep(bh_ctx *c, float theta, hipStream_t st);
+
+// walk.hip
+void launch_walk(bh_ctx *c, float eps, hipStream_t st);
+int walk_blocks_per_cu();
+
+// integrate.hip
+void launch_ingest(bh_ctx *c, const float *pos, const float *vel, const float *mass, uint32_t n,
+                   hipStream_t st);
+void launch_kick(bh_ctx *c, float h, uint32_t n, hipStream_t st);
+void launch_kick_drift(bh_ctx *c, float h, float dt, uint32_t n, hipStream_t st);
+void launch_unsort(bh_ctx *c, float *acc, float *pot, uint32_t n, hipStream_t st);
+void launch_state_out(bh_ctx *c, float *pos, float *vel, uint32_t n, hipStream_t st);
+void launch_totals(bh_ctx *c, uint32_t n, hipStream_t st);
+void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
+
+inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+}  // namespace bh

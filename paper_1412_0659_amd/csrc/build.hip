@@ -1,0 +1,231 @@
+// Octree construction from sorted Morton keys, level by level (Sec. I.A:
+// octants are split until a cell holds at most nleaf particles; Table II
+// "Tree-construction"), and the target groups of the walk.
+//
+// Cells are numbered breadth first: the cells of level l, in key order,
+// then those of level l + 1.  A cell (l, P) with more than nleaf particles
+// and l < 21 gets one child per non-empty 3-bit digit d, found by binary
+// search for the key bound (8 P + d) << 3 (20 - l) inside the cell's range.
+// Each level takes three launches over a fixed grid that reads the level's
+// cell range from device memory (count children / scan block totals / write
+// children), so the build never waits on the host.
+#include "bh_internal.h"
+#include "wave.h"
+
+namespace bh {
+
+constexpr int kBuildThreads = 256;
+
+__device__ __forceinline__ uint32_t key_lower_bound(const uint64_t *__restrict__ k, uint32_t lo,
+                                                    uint32_t hi, uint64_t v) {
+    while (lo < hi) {
+        uint32_t mid = lo + ((hi - lo) >> 1);
+        if (k[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// digit boundaries of the children of cell c (level l): bnd[0] = begin,
+// bnd[8] = end; child d holds [bnd[d], bnd[d+1])
+__device__ __forceinline__ void child_bounds(const uint64_t *__restrict__ key, uint64_t P,
+                                             uint32_t b, uint32_t e, int l, uint32_t bnd[9]) {
+    uint32_t shift = 3u * (kKeyBits - 1 - l);
+    bnd[0] = b;
+#pragma unroll
+    for (uint32_t d = 1; d < 8; ++d)
+        bnd[d] = key_lower_bound(key, bnd[d - 1], e, ((P << 3) | d) << shift);
+    bnd[8] = e;
+}
+
+__global__ void k_build_init(Cells c, uint32_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        c.prefix[0] = 0;
+        c.level[0] = 0;
+        c.begin[0] = 0;
+        c.count[0] = n;
+        c.child0[0] = kNone;
+        c.nchild[0] = 0;
+        c.parent[0] = kNone;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < kLsSize) c.ls[threadIdx.x] = threadIdx.x == 0 ? 0u : 1u;
+}
+
+__device__ __forceinline__ void level_chunk(const Cells &c, int l, uint32_t &cs, uint32_t &ce) {
+    uint32_t first = c.ls[l], last = c.ls[l + 1];
+    uint32_t chunk = (last - first + gridDim.x - 1) / gridDim.x;
+    cs = first + blockIdx.x * chunk;
+    ce = min(last, cs + chunk);
+    if (cs > ce) cs = ce;
+}
+
+__global__ __launch_bounds__(kBuildThreads) void k_build_count(Cells c,
+                                                               const uint64_t *__restrict__ key,
+                                                               int l, uint32_t nleaf) {
+    __shared__ uint32_t lds[4];
+    uint32_t cs, ce;
+    level_chunk(c, l, cs, ce);
+    uint32_t sum = 0;
+    for (uint32_t i = cs + threadIdx.x; i < ce; i += kBuildThreads) {
+        uint32_t nch = 0;
+        uint32_t cnt = c.count[i];
+        if (cnt > nleaf) {
+            uint32_t bnd[9];
+            uint32_t b = c.begin[i];
+            child_bounds(key, c.prefix[i], b, b + cnt, l, bnd);
+#pragma unroll
+            for (int d = 0; d < 8; ++d) nch += bnd[d + 1] > bnd[d];
+        }
+        c.nchild[i] = nch;
+        sum += nch;
+    }
+    sum = wave_sum(sum);
+    if (lane_id() == 0) lds[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) c.part[blockIdx.x] = lds[0] + lds[1] + lds[2] + lds[3];
+}
+
+// exclusive scan of the kGrid block totals; sets the end of level l + 1
+__global__ __launch_bounds__(kBuildThreads) void k_build_scan(Cells c, int l, uint32_t cap,
+                                                              uint32_t *status) {
+    __shared__ uint32_t lds[4];
+    constexpr int per = kGrid / kBuildThreads;
+    uint32_t v[per], s = 0;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        v[k] = c.part[threadIdx.x * per + k];
+        s += v[k];
+    }
+    uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t inc = wave_incl_scan(s, lane);
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (uint32_t k = 0; k < 4; ++k) {
+        if (k < w) off += lds[k];
+        tot += lds[k];
+    }
+    off += inc - s;
+#pragma unroll
+    for (int k = 0; k < per; ++k) {
+        c.part[threadIdx.x * per + k] = off;
+        off += v[k];
+    }
+    if (threadIdx.x == 0) {
+        uint32_t end = c.ls[l + 1] + tot;
+        if (end > cap) {
+            atomicOr(status, kStOverflow);
+            end = cap;
+        }
+        c.ls[l + 2] = end;
+    }
+}
+
+__global__ __launch_bounds__(kBuildThreads) void k_build_write(Cells c,
+                                                               const uint64_t *__restrict__ key,
+                                                               int l, uint32_t cap) {
+    __shared__ uint32_t lds[4];
+    uint32_t cs, ce;
+    level_chunk(c, l, cs, ce);
+    uint32_t carry = c.ls[l + 1] + c.part[blockIdx.x];
+    uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    for (uint32_t base = cs; base < ce; base += kBuildThreads) {
+        uint32_t i = base + threadIdx.x;
+        uint32_t v = i < ce ? c.nchild[i] : 0u;
+        uint32_t inc = wave_incl_scan(v, lane);
+        if (lane == 63) lds[w] = inc;
+        __syncthreads();
+        uint32_t off = 0, tot = 0;
+        for (uint32_t k = 0; k < 4; ++k) {
+            if (k < w) off += lds[k];
+            tot += lds[k];
+        }
+        __syncthreads();
+        if (v > 0) {
+            uint32_t ch = carry + off + inc - v;
+            c.child0[i] = ch;
+            uint32_t b = c.begin[i];
+            uint64_t P = c.prefix[i];
+            uint32_t bnd[9];
+            child_bounds(key, P, b, b + c.count[i], l, bnd);
+            for (uint32_t d = 0; d < 8; ++d) {
+                if (bnd[d + 1] > bnd[d]) {
+                    if (ch < cap) {
+                        c.prefix[ch] = (P << 3) | d;
+                        c.level[ch] = (uint32_t)(l + 1);
+                        c.begin[ch] = bnd[d];
+                        c.count[ch] = bnd[d + 1] - bnd[d];
+                        c.child0[ch] = kNone;
+                        c.nchild[ch] = 0;
+                        c.parent[ch] = i;
+                    }
+                    ++ch;
+                }
+            }
+        } else if (i < ce) {
+            c.child0[i] = kNone;
+        }
+        carry += tot;
+    }
+}
+
+void launch_build(bh_ctx *ctx, uint32_t n, hipStream_t st) {
+    Cells &c = ctx->cells;
+    hipLaunchKernelGGL(k_build_init, dim3(1), dim3(64), 0, st, c, n);
+    uint32_t cap = (uint32_t)ctx->cap_cells;
+    for (int l = 0; l < kLevels - 1; ++l) {
+        hipLaunchKernelGGL(k_build_count, dim3(kGrid), dim3(kBuildThreads), 0, st, c,
+                           (const uint64_t *)ctx->sort.key[0], l, (uint32_t)ctx->p.nleaf);
+        hipLaunchKernelGGL(k_build_scan, dim3(1), dim3(kBuildThreads), 0, st, c, l, cap,
+                           ctx->status);
+        hipLaunchKernelGGL(k_build_write, dim3(kGrid), dim3(kBuildThreads), 0, st, c,
+                           (const uint64_t *)ctx->sort.key[0], l, cap);
+    }
+}
+
+// ---- groups -----------------------------------------------------------------
+//
+// A cell is a group iff (count <= ncrit or it is a leaf) and (it is the root
+// or its parent holds more than ncrit).  Groups partition the sorted
+// particles; a group cell larger than ncrit (a level-21 leaf of coincident
+// keys) is cut into chunks of ncrit.  Group numbers follow key order: flag
+// each group's first particle, scan the flags.
+
+__global__ __launch_bounds__(256) void k_group_flags(Cells c, uint32_t ncrit, uint32_t *flag) {
+    uint32_t nc = c.ls[kLevels];
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) {
+        uint32_t cnt = c.count[i];
+        bool small = cnt <= ncrit || c.nchild[i] == 0;
+        bool top = i == 0 || c.count[c.parent[i]] > ncrit;
+        if (small && top) {
+            uint32_t b = c.begin[i];
+            for (uint32_t s = 0; s < cnt; s += ncrit) flag[b + s] = 1u;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_group_fill(const uint32_t *__restrict__ flag,
+                                                    const uint32_t *__restrict__ scan, uint32_t n,
+                                                    uint32_t *gbeg, uint32_t *ngroups) {
+    uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    if (flag[i]) gbeg[scan[i]] = i;
+    if (i == n - 1) {
+        uint32_t ng = scan[i] + flag[i];
+        *ngroups = ng;
+        gbeg[ng] = n;
+    }
+}
+
+void launch_groups(bh_ctx *ctx, uint32_t n, hipStream_t st) {
+    Groups &g = ctx->groups;
+    launch_fill_u32(g.flag, 0u, n, st);
+    hipLaunchKernelGGL(k_group_flags, dim3(kGrid), dim3(256), 0, st, ctx->cells,
+                       (uint32_t)ctx->p.ncrit, g.flag);
+    launch_exclusive_scan(g.flag, g.scan, n, ctx->sort.scan_part, st);
+    hipLaunchKernelGGL(k_group_fill, dim3(cdiv(n, 256)), dim3(256), 0, st,
+                       (const uint32_t *)g.flag, (const uint32_t *)g.scan, n, g.begin,
+                       g.count_dev);
+}
+
+}  // namespace bh

@@ -1,0 +1,173 @@
+// Particle state in and out of the sorted layout, the leapfrog kicks and
+// drift (Sec. III.B.2: second-order leap-frog after the forces), and the
+// interaction totals of a walk (Sec. VI.A: flops = 23 per particle-particle
+// and 65 per particle-cell interaction, counted during execution).
+#include "bh_internal.h"
+#include "wave.h"
+
+namespace bh {
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * 256)
+        p[i] = v;
+}
+
+void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st) {
+    uint32_t nb = cdiv(n, 256);
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_fill_u32, dim3(nb), dim3(256), 0, st, p, v, n);
+}
+
+// caller [n][3] positions / velocities and [n] masses -> state (caller order)
+__global__ __launch_bounds__(256) void k_ingest(const float *__restrict__ pos,
+                                                const float *__restrict__ vel,
+                                                const float *__restrict__ mass, uint32_t n,
+                                                State s, uint32_t *status) {
+    uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    s.x[i] = pos[3 * (size_t)i];
+    s.y[i] = pos[3 * (size_t)i + 1];
+    s.z[i] = pos[3 * (size_t)i + 2];
+    float mi = mass[i];
+    s.m[i] = mi;
+    if (!(mi > 0.f) || !isfinite(mi)) atomicOr(status, kStMass);
+    if (vel) {
+        float a = vel[3 * (size_t)i], b = vel[3 * (size_t)i + 1], c = vel[3 * (size_t)i + 2];
+        if (!(isfinite(a) && isfinite(b) && isfinite(c))) atomicOr(status, kStNonFinite);
+        s.vx[i] = a;
+        s.vy[i] = b;
+        s.vz[i] = c;
+    } else {
+        s.vx[i] = 0.f;
+        s.vy[i] = 0.f;
+        s.vz[i] = 0.f;
+    }
+    s.cid[i] = i;
+}
+
+void launch_ingest(bh_ctx *c, const float *pos, const float *vel, const float *mass, uint32_t n,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_ingest, dim3(cdiv(n, 256)), dim3(256), 0, st, pos, vel, mass, n,
+                       c->st[c->cur], c->status);
+}
+
+// v += a h
+__global__ __launch_bounds__(256) void k_kick(State s, const float4 *__restrict__ acc, uint32_t n,
+                                              float h) {
+    uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float4 a = acc[i];
+    s.vx[i] = fmaf(a.x, h, s.vx[i]);
+    s.vy[i] = fmaf(a.y, h, s.vy[i]);
+    s.vz[i] = fmaf(a.z, h, s.vz[i]);
+}
+
+// v += a h; x += v dt
+__global__ __launch_bounds__(256) void k_kick_drift(State s, const float4 *__restrict__ acc,
+                                                    uint32_t n, float h, float dt) {
+    uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float4 a = acc[i];
+    float vx = fmaf(a.x, h, s.vx[i]), vy = fmaf(a.y, h, s.vy[i]), vz = fmaf(a.z, h, s.vz[i]);
+    s.vx[i] = vx;
+    s.vy[i] = vy;
+    s.vz[i] = vz;
+    s.x[i] = fmaf(vx, dt, s.x[i]);
+    s.y[i] = fmaf(vy, dt, s.y[i]);
+    s.z[i] = fmaf(vz, dt, s.z[i]);
+}
+
+void launch_kick(bh_ctx *c, float h, uint32_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_kick, dim3(cdiv(n, 256)), dim3(256), 0, st, c->st[c->cur],
+                       (const float4 *)c->acc, n, h);
+}
+
+void launch_kick_drift(bh_ctx *c, float h, float dt, uint32_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_kick_drift, dim3(cdiv(n, 256)), dim3(256), 0, st, c->st[c->cur],
+                       (const float4 *)c->acc, n, h, dt);
+}
+
+// sorted acceleration + potential -> caller order
+__global__ __launch_bounds__(256) void k_unsort(const float4 *__restrict__ acc,
+                                                const uint32_t *__restrict__ cid, uint32_t n,
+                                                float *__restrict__ out_acc,
+                                                float *__restrict__ out_pot) {
+    uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float4 a = acc[i];
+    uint32_t p = cid[i];
+    if (out_acc) {
+        out_acc[3 * (size_t)p] = a.x;
+        out_acc[3 * (size_t)p + 1] = a.y;
+        out_acc[3 * (size_t)p + 2] = a.z;
+    }
+    if (out_pot) out_pot[p] = a.w;
+}
+
+void launch_unsort(bh_ctx *c, float *acc, float *pot, uint32_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_unsort, dim3(cdiv(n, 256)), dim3(256), 0, st, (const float4 *)c->acc,
+                       (const uint32_t *)c->st[c->cur].cid, n, acc, pot);
+}
+
+__global__ __launch_bounds__(256) void k_state_out(State s, uint32_t n, float *__restrict__ pos,
+                                                   float *__restrict__ vel) {
+    uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    uint32_t p = s.cid[i];
+    if (pos) {
+        pos[3 * (size_t)p] = s.x[i];
+        pos[3 * (size_t)p + 1] = s.y[i];
+        pos[3 * (size_t)p + 2] = s.z[i];
+    }
+    if (vel) {
+        vel[3 * (size_t)p] = s.vx[i];
+        vel[3 * (size_t)p + 1] = s.vy[i];
+        vel[3 * (size_t)p + 2] = s.vz[i];
+    }
+}
+
+void launch_state_out(bh_ctx *c, float *pos, float *vel, uint32_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_state_out, dim3(cdiv(n, 256)), dim3(256), 0, st, c->st[c->cur], n, pos,
+                       vel);
+}
+
+// sum over groups of npp * size and npc * size (integers: order-free)
+__global__ __launch_bounds__(256) void k_totals(const uint32_t *__restrict__ gbeg,
+                                                const uint32_t *__restrict__ ngroups,
+                                                const uint32_t *__restrict__ npp,
+                                                const uint32_t *__restrict__ npc,
+                                                unsigned long long *tot) {
+    uint32_t ng = *ngroups;
+    unsigned long long spp = 0, spc = 0;
+    for (uint32_t g = blockIdx.x * 256 + threadIdx.x; g < ng; g += gridDim.x * 256) {
+        unsigned long long sz = gbeg[g + 1] - gbeg[g];
+        spp += sz * npp[g];
+        spc += sz * npc[g];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        spp += __shfl_xor(spp, d, 64);
+        spc += __shfl_xor(spc, d, 64);
+    }
+    if (lane_id() == 0) {
+        atomicAdd(&tot[0], spp);
+        atomicAdd(&tot[1], spc);
+    }
+}
+
+__global__ void k_zero_totals(unsigned long long *tot) {
+    if (threadIdx.x < 2) tot[threadIdx.x] = 0ull;
+}
+
+void launch_totals(bh_ctx *c, uint32_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_totals, dim3(1), dim3(64), 0, st, c->totals);
+    uint32_t nb = cdiv(n, 256);
+    if (nb > 1024) nb = 1024;
+    hipLaunchKernelGGL(k_totals, dim3(nb), dim3(256), 0, st, (const uint32_t *)c->groups.begin,
+                       (const uint32_t *)c->groups.count_dev, (const uint32_t *)c->groups.npp,
+                       (const uint32_t *)c->groups.npc, c->totals);
+}
+
+}  // namespace bh

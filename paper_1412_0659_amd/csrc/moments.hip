@@ -1,0 +1,154 @@
+// Upward pass: mass, centre of mass and quadrupole of every cell in FP64
+// (Sec. I.A: multipole moments computed once the tree is built; Sec. VI.A
+// Eq. (1): the quadrupole is the 3x3 second moment of the cell's mass about
+// its centre of mass; Table II "Tree-properties").
+//
+//   leaf:   M = sum m, S = sum m x, com = S / M, Q = sum m s s^T, s = x - com
+//   parent: M = sum M_c, S = sum S_c, com = S / M,
+//           Q = sum (Q_c + M_c d d^T), d = com_c - com   (parallel axis)
+//
+// Each cell is one thread summing in a fixed order (a leaf over its
+// particles in sorted order, a parent over its children in child order),
+// with contraction off, so the result does not depend on the launch.  Leaves
+// first, then internal cells level by level from the deepest.  The walk
+// reads FP32 copies: com, M, Q, and the opening radius
+// r_open = l / theta + |com - geometric centre| (l = cell size).
+#include "bh_internal.h"
+
+namespace bh {
+
+__global__ __launch_bounds__(256) void k_moments_leaf(Cells c, const float *__restrict__ x,
+                                                      const float *__restrict__ y,
+                                                      const float *__restrict__ z,
+                                                      const float *__restrict__ m) {
+    uint32_t nc = c.ls[kLevels];
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) {
+        if (c.nchild[i] != 0) continue;
+        uint32_t b = c.begin[i], e = b + c.count[i];
+        double mm = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (uint32_t j = b; j < e; ++j) {
+            double mj = m[j];
+            mm = mm + mj;
+            s0 = s0 + mj * (double)x[j];
+            s1 = s1 + mj * (double)y[j];
+            s2 = s2 + mj * (double)z[j];
+        }
+        double c0 = s0 / mm, c1 = s1 / mm, c2 = s2 / mm;
+        double q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0;
+        for (uint32_t j = b; j < e; ++j) {
+            double mj = m[j];
+            double d0 = (double)x[j] - c0, d1 = (double)y[j] - c1, d2 = (double)z[j] - c2;
+            q0 = q0 + (mj * d0) * d0;
+            q1 = q1 + (mj * d1) * d1;
+            q2 = q2 + (mj * d2) * d2;
+            q3 = q3 + (mj * d0) * d1;
+            q4 = q4 + (mj * d0) * d2;
+            q5 = q5 + (mj * d1) * d2;
+        }
+        c.M[i] = mm;
+        c.S[3 * i] = s0; c.S[3 * i + 1] = s1; c.S[3 * i + 2] = s2;
+        c.com[3 * i] = c0; c.com[3 * i + 1] = c1; c.com[3 * i + 2] = c2;
+        double *q = c.Q + 6 * (size_t)i;
+        q[0] = q0; q[1] = q1; q[2] = q2; q[3] = q3; q[4] = q4; q[5] = q5;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_moments_up(Cells c, int l) {
+    uint32_t first = c.ls[l], last = c.ls[l + 1];
+    for (uint32_t i = first + blockIdx.x * 256 + threadIdx.x; i < last;
+         i += gridDim.x * 256) {
+        uint32_t nch = c.nchild[i];
+        if (nch == 0) continue;
+        uint32_t k0 = c.child0[i], k1 = k0 + nch;
+        double mm = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (uint32_t k = k0; k < k1; ++k) {
+            mm = mm + c.M[k];
+            s0 = s0 + c.S[3 * k];
+            s1 = s1 + c.S[3 * k + 1];
+            s2 = s2 + c.S[3 * k + 2];
+        }
+        double c0 = s0 / mm, c1 = s1 / mm, c2 = s2 / mm;
+        double q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0;
+        for (uint32_t k = k0; k < k1; ++k) {
+            double mk = c.M[k];
+            double d0 = c.com[3 * k] - c0, d1 = c.com[3 * k + 1] - c1, d2 = c.com[3 * k + 2] - c2;
+            const double *qk = c.Q + 6 * (size_t)k;
+            q0 = q0 + (qk[0] + (mk * d0) * d0);
+            q1 = q1 + (qk[1] + (mk * d1) * d1);
+            q2 = q2 + (qk[2] + (mk * d2) * d2);
+            q3 = q3 + (qk[3] + (mk * d0) * d1);
+            q4 = q4 + (qk[4] + (mk * d0) * d2);
+            q5 = q5 + (qk[5] + (mk * d1) * d2);
+        }
+        c.M[i] = mm;
+        c.S[3 * i] = s0; c.S[3 * i + 1] = s1; c.S[3 * i + 2] = s2;
+        c.com[3 * i] = c0; c.com[3 * i + 1] = c1; c.com[3 * i + 2] = c2;
+        double *q = c.Q + 6 * (size_t)i;
+        q[0] = q0; q[1] = q1; q[2] = q2; q[3] = q3; q[4] = q4; q[5] = q5;
+    }
+}
+
+// corner coordinates of a cell from its key prefix (x the high bit of each digit)
+__device__ __forceinline__ void cell_coords(uint64_t prefix, uint32_t lev, uint32_t p[3]) {
+    uint32_t a = 0, b = 0, d = 0;
+    for (int s = (int)lev - 1; s >= 0; --s) {
+        uint32_t dig = (uint32_t)(prefix >> (3 * s)) & 7u;
+        a = (a << 1) | (dig >> 2);
+        b = (b << 1) | ((dig >> 1) & 1u);
+        d = (d << 1) | (dig & 1u);
+    }
+    p[0] = a; p[1] = b; p[2] = d;
+}
+
+__global__ __launch_bounds__(256) void k_moments_final(Cells c, const float *__restrict__ box) {
+    uint32_t nc = c.ls[kLevels];
+    double lo0 = box[0], lo1 = box[1], lo2 = box[2], side = box[3];
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) {
+        uint32_t lev = c.level[i];
+        uint32_t p[3];
+        cell_coords(c.prefix[i], lev, p);
+        double lc = side * (1.0 / (double)(1u << lev));
+        double c0 = c.com[3 * i], c1 = c.com[3 * i + 1], c2 = c.com[3 * i + 2];
+        double e0 = c0 - (lo0 + ((double)p[0] + 0.5) * lc);
+        double e1 = c1 - (lo1 + ((double)p[1] + 0.5) * lc);
+        double e2 = c2 - (lo2 + ((double)p[2] + 0.5) * lc);
+        double dl = __dsqrt_rn((e0 * e0 + e1 * e1) + e2 * e2);
+        const double *q = c.Q + 6 * (size_t)i;
+        double tr = (q[0] + q[1]) + q[2];
+        c.wA[i] = make_float4((float)c0, (float)c1, (float)c2, 0.f);
+        c.wM[i] = make_float4((float)c.M[i], (float)q[0], (float)q[1], (float)q[2]);
+        c.wQ[i] = make_float4((float)q[3], (float)q[4], (float)q[5], (float)(0.5 * tr));
+        c.trm[i] = (float)(-1.5 * tr);
+        uint32_t nch = c.nchild[i];
+        c.wN[i] = nch ? make_uint2(c.child0[i], nch) : make_uint2(c.begin[i], c.count[i] | kLeafBit);
+        c.size[i] = make_float2((float)lc, (float)dl);
+    }
+}
+
+void launch_moments(bh_ctx *ctx, hipStream_t st) {
+    const State &s = ctx->st[ctx->cur];
+    Cells &c = ctx->cells;
+    hipLaunchKernelGGL(k_moments_leaf, dim3(kGrid * 2), dim3(256), 0, st, c,
+                       (const float *)s.x, (const float *)s.y, (const float *)s.z,
+                       (const float *)s.m);
+    for (int l = kLevels - 2; l >= 0; --l)
+        hipLaunchKernelGGL(k_moments_up, dim3(kGrid), dim3(256), 0, st, c, l);
+    hipLaunchKernelGGL(k_moments_final, dim3(kGrid * 2), dim3(256), 0, st, c,
+                       (const float *)ctx->box);
+}
+
+// r_open^2 = (fl32(l / theta) + delta)^2 in FP32, stored in wA.w
+__global__ __launch_bounds__(256) void k_walk_prep(Cells c, float theta) {
+    uint32_t nc = c.ls[kLevels];
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) {
+        float2 sz = c.size[i];
+        float r = sz.x / theta + sz.y;
+        c.wA[i].w = r * r;
+    }
+}
+
+void launch_walk_prep(bh_ctx *ctx, float theta, hipStream_t st) {
+    hipLaunchKernelGGL(k_walk_prep, dim3(kGrid * 2), dim3(256), 0, st, ctx->cells, theta);
+}
+
+}  // namespace bh

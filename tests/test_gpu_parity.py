@@ -1,0 +1,177 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Integer work (keys, sort permutation, octree cells, groups, interaction
+counts) must be bit-exact; the FP32 forces must match the FP64 oracle tree
+within 1e-5 median / 1e-4 99th-percentile relative error.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import assert_tree_equal, gpu_force, gpu_tree, rel_err, to_dev
+from workloads import ics
+
+pytestmark = pytest.mark.gpu
+
+MED_TOL, P99_TOL = 1e-5, 1e-4
+
+
+def _cases():
+    rng = np.random.default_rng(5)
+    s = ics.plummer(16384, 1)
+    yield "plummer_16k", s.pos, s.mass
+    d = ics.disk_halo(20000, 80000, 12)
+    yield "disk_halo_100k", d.pos, d.mass
+    # ragged size, clustered with exact duplicates and a far outlier
+    pos = np.concatenate([rng.normal(size=(3001, 3)) * 1e-3, np.full((90, 3), 0.125),
+                          rng.uniform(-50, 50, (1500, 3)), [[1e4, -1e4, 3.0]]]).astype(np.float32)
+    m = rng.uniform(0.5, 2.0, pos.shape[0]).astype(np.float32)
+    yield "clustered_ragged", pos, m
+
+
+CASES = list(_cases())
+
+
+@pytest.mark.parametrize("name,pos,mass", CASES, ids=[c[0] for c in CASES])
+def test_tree_bit_exact(oracle, name, pos, mass):
+    print(f"case {name} n={len(mass)}", flush=True)
+    t = gpu_tree(pos, mass)
+    ot = oracle.build_tree(pos, mass)
+    assert_tree_equal(t, ot)
+    # moments: the same FP64 operation order as the oracle -> identical bits
+    nc = ot.cells["ncell"]
+    assert np.array_equal(t.export("mom_M"), ot.mom["M"])
+    assert np.array_equal(t.export("mom_com"), ot.mom["com"])
+    assert np.array_equal(t.export("mom_Q"), ot.mom["Q"])
+    comf = t.export("cell_comf")
+    assert np.array_equal(comf[:, :3], ot.mom["comf"])
+    size = t.export("cell_size")
+    assert np.array_equal(size[:, 0], ot.mom["lf"]) and np.array_equal(size[:, 1], ot.mom["deltaf"])
+    assert comf.shape[0] == nc
+    t.close()
+
+
+@pytest.mark.parametrize("name,pos,mass", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("theta,eps", [(0.5, 0.01), (0.4, 0.005), (0.75, 0.0)])
+def test_walk_parity(oracle, name, pos, mass, theta, eps):
+    print(f"case {name} n={len(mass)} theta={theta} eps={eps}", flush=True)
+    t = gpu_tree(pos, mass)
+    acc, pot = gpu_force(t, theta, eps)
+    ot = oracle.build_tree(pos, mass)
+    oacc, opot, onpp, onpc = oracle.walk(ot, theta, eps)
+    # the opening decisions (and so the interaction lists) are identical
+    box = t.export("group_box")
+    assert np.array_equal(box[:, :3], ot.gc) and np.array_equal(box[:, 4:7], ot.gh)
+    assert np.array_equal(t.export("group_npp").astype(np.int64), onpp)
+    assert np.array_equal(t.export("group_npc").astype(np.int64), onpc)
+    comf = t.export("cell_comf")
+    assert np.array_equal(comf[:, 3], oracle.open_radius2(ot.mom["lf"], ot.mom["deltaf"], theta))
+    st = t.stats()
+    assert st["n_pp"] == int((onpp * ot.gcnt).sum()) and st["n_pc"] == int((onpc * ot.gcnt).sum())
+    ea = rel_err(acc, oacc)
+    ep = rel_err(pot, opot)
+    print(f"  acc med {np.median(ea):.2e} p99 {np.percentile(ea, 99):.2e}  "
+          f"pot med {np.median(ep):.2e} p99 {np.percentile(ep, 99):.2e}", flush=True)
+    assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
+    assert np.median(ep) <= MED_TOL and np.percentile(ep, 99) <= P99_TOL
+    t.close()
+
+
+def test_walk_deterministic(oracle):
+    s = ics.disk_halo(10000, 40000, 13)
+    t = gpu_tree(s.pos, s.mass)
+    a1, p1 = gpu_force(t, 0.4, 0.005)
+    a2, p2 = gpu_force(t, 0.4, 0.005)
+    assert np.array_equal(a1, a2) and np.array_equal(p1, p2)
+    t.close()
+
+
+def test_small_theta_is_direct(oracle):
+    s = ics.plummer(4096, 8)
+    t = gpu_tree(s.pos, s.mass)
+    acc, pot = gpu_force(t, 1e-6, 0.01)
+    assert np.all(t.export("group_npc") == 0)
+    ad, pd = oracle.direct(s.pos, s.mass, 0.01)
+    ea, ep = rel_err(acc, ad), rel_err(pot, pd)
+    assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
+    assert np.median(ep) <= MED_TOL and np.percentile(ep, 99) <= P99_TOL
+    t.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 17, 65, 1000])
+def test_small_and_ragged_sizes(oracle, n):
+    s = ics.plummer(n, 200 + n)
+    t = gpu_tree(s.pos, s.mass)
+    acc, pot = gpu_force(t, 0.6, 0.02)
+    ot = oracle.build_tree(s.pos, s.mass)
+    assert_tree_equal(t, ot)
+    oacc, opot, onpp, onpc = oracle.walk(ot, 0.6, 0.02)
+    assert np.array_equal(t.export("group_npc").astype(np.int64), onpc)
+    if n == 1:
+        assert np.all(acc == 0) and np.all(pot == 0)
+    else:
+        assert np.percentile(rel_err(acc, oacc), 99) <= P99_TOL
+        assert np.percentile(rel_err(pot, opot), 99) <= P99_TOL
+    t.close()
+
+
+def test_coincident_points(oracle):
+    """Coincident keys: a chain to a level-21 leaf larger than a group."""
+    rng = np.random.default_rng(3)
+    pos = np.concatenate([np.full((150, 3), 0.3), rng.uniform(0, 1, (500, 3))]).astype(np.float32)
+    m = np.full(pos.shape[0], 1.0 / pos.shape[0], np.float32)
+    t = gpu_tree(pos, m)
+    ot = oracle.build_tree(pos, m)
+    assert_tree_equal(t, ot)
+    acc, pot = gpu_force(t, 0.5, 0.01)
+    oacc, opot, onpp, onpc = oracle.walk(ot, 0.5, 0.01)
+    assert np.array_equal(t.export("group_npp").astype(np.int64), onpp)
+    assert np.percentile(rel_err(pot, opot), 99) <= P99_TOL
+    # the coincident particles have a ~zero net force; compare absolutely
+    assert np.max(np.abs(acc - oacc)) <= 1e-4 * np.max(np.abs(oacc))
+    t.close()
+
+
+@pytest.mark.parametrize("nleaf,ncrit", [(1, 1), (8, 32), (16, 64), (64, 16)])
+def test_tree_parameters(oracle, nleaf, ncrit):
+    s = ics.disk_halo(2000, 8000, 14)
+    t = gpu_tree(s.pos, s.mass, nleaf, ncrit)
+    ot = oracle.build_tree(s.pos, s.mass, nleaf, ncrit)
+    assert_tree_equal(t, ot)
+    acc, pot = gpu_force(t, 0.5, 0.01)
+    oacc, opot, onpp, onpc = oracle.walk(ot, 0.5, 0.01)
+    assert np.array_equal(t.export("group_npp").astype(np.int64), onpp)
+    assert np.array_equal(t.export("group_npc").astype(np.int64), onpc)
+    assert np.median(rel_err(acc, oacc)) <= MED_TOL
+    t.close()
+
+
+def test_errors_and_state():
+    import paper_1412_0659_amd as bh
+    s = ics.plummer(1000, 9)
+    t = bh.Tree(1000)
+    with pytest.raises(bh.BhError) as e:
+        t.force(0.5, 0.01)
+    assert e.value.code == bh.binding.BH_ESTATE
+    with pytest.raises(bh.BhError) as e:
+        bh.tree_build(t.ctx, to_dev(np.zeros((1001, 3))), to_dev(np.ones(1001)))
+    assert e.value.code == bh.binding.BH_ECAPACITY
+    t.build(to_dev(s.pos), to_dev(s.mass))
+    for theta, eps in [(0.0, 0.01), (1.5, 0.01), (float("nan"), 0.01), (0.5, -1.0)]:
+        with pytest.raises(bh.BhError) as e:
+            t.force(theta, eps)
+        assert e.value.code == bh.binding.BH_EINVAL
+    bad = s.mass.copy()
+    bad[7] = 0.0
+    t.build(to_dev(s.pos), to_dev(bad))
+    with pytest.raises(bh.BhError) as e:
+        t.sync()
+    assert e.value.code == bh.binding.BH_EMASS
+    p = s.pos.copy()
+    p[3, 1] = np.nan
+    t.build(to_dev(p), to_dev(s.mass))
+    with pytest.raises(bh.BhError) as e:
+        t.sync()
+    assert e.value.code == bh.binding.BH_ENONFINITE
+    t.build(to_dev(s.pos), to_dev(s.mass))
+    t.sync()
+    t.close()
