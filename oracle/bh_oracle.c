@@ -440,3 +440,266 @@ void orc_expansion(int64_t nt, const double *tpos, double mc, const double *comc
         interact(&tpos[3 * k], comc, mc, qc, eps * eps, &acc[3 * k], &pot[k], 1);
     }
 }
+
+/* ---------------------------------------------------------------------------
+ * Differentiation with frozen decisions.
+ *
+ * The walk's decisions (which cells each group accepts, which leaves it
+ * opens) and the tree topology are recorded once and held fixed; the force
+ * is then a smooth function of the positions and masses through Eq. (1)-(2)
+ * and through the moments of the accepted cells.  orc_walk_record stores the
+ * decisions; orc_replay evaluates the force for new (x, m) with them (FP64
+ * positions, so finite differences can perturb them); orc_replay_vjp is the
+ * hand-written adjoint: u -> (u^T da/dx, u^T da/dm).
+ * ------------------------------------------------------------------------- */
+
+/* Record the decisions of the walk for groups [0, ng): per group g the
+ * accepted cells pc[pc_off[g] .. pc_off[g+1]) and opened leaves
+ * lf[lf_off[g] .. lf_off[g+1]).  With pc == NULL only the offsets are
+ * filled (counts prefix-summed), so the caller can size the lists. */
+void orc_walk_record(int64_t ng, const int64_t *gbeg, const int64_t *gcnt, const float *gc,
+                     const float *gh, int64_t ncell, const int64_t *child0,
+                     const int32_t *nchild, const float *comf, const float *ropen2,
+                     int64_t *pc_off, int64_t *pc, int64_t *lf_off, int64_t *lf) {
+    (void)gbeg;
+    (void)gcnt;
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)ncell);
+    int64_t npc = 0, nlf = 0;
+    pc_off[0] = 0;
+    lf_off[0] = 0;
+    for (int64_t g = 0; g < ng; ++g) {
+        int64_t head = 0, tail = 0;
+        queue[tail++] = 0;
+        while (head < tail) {
+            int64_t c = queue[head++];
+            if (mac_accept(&comf[3 * c], ropen2[c], &gc[3 * g], &gh[3 * g])) {
+                if (pc) pc[npc] = c;
+                ++npc;
+            } else if (nchild[c] == 0) {
+                if (lf) lf[nlf] = c;
+                ++nlf;
+            } else {
+                for (int64_t ch = child0[c]; ch < child0[c] + nchild[c]; ++ch) queue[tail++] = ch;
+            }
+        }
+        pc_off[g + 1] = npc;
+        lf_off[g + 1] = nlf;
+    }
+    free(queue);
+}
+
+/* Moments of every cell from FP64 positions with a fixed topology
+ * (the upward pass of orc_moments, without the FP32 copies). */
+static void moments64(int64_t ncell, const int64_t *begin, const int64_t *count,
+                      const int64_t *child0, const int32_t *nchild, const double *x,
+                      const double *m, double *M, double *com, double *Q) {
+    for (int64_t c = ncell - 1; c >= 0; --c) {
+        double mm = 0.0, s[3] = {0, 0, 0}, q[6] = {0, 0, 0, 0, 0, 0}, cm[3];
+        if (nchild[c] == 0) {
+            for (int64_t j = begin[c]; j < begin[c] + count[c]; ++j) {
+                mm += m[j];
+                for (int a = 0; a < 3; ++a) s[a] += m[j] * x[3 * j + a];
+            }
+            for (int a = 0; a < 3; ++a) cm[a] = s[a] / mm;
+            for (int64_t j = begin[c]; j < begin[c] + count[c]; ++j) {
+                double d[3] = {x[3 * j] - cm[0], x[3 * j + 1] - cm[1], x[3 * j + 2] - cm[2]};
+                q[0] += m[j] * d[0] * d[0];
+                q[1] += m[j] * d[1] * d[1];
+                q[2] += m[j] * d[2] * d[2];
+                q[3] += m[j] * d[0] * d[1];
+                q[4] += m[j] * d[0] * d[2];
+                q[5] += m[j] * d[1] * d[2];
+            }
+        } else {
+            for (int64_t k = child0[c]; k < child0[c] + nchild[c]; ++k) {
+                mm += M[k];
+                for (int a = 0; a < 3; ++a) s[a] += M[k] * com[3 * k + a];
+            }
+            for (int a = 0; a < 3; ++a) cm[a] = s[a] / mm;
+            for (int64_t k = child0[c]; k < child0[c] + nchild[c]; ++k) {
+                double d[3] = {com[3 * k] - cm[0], com[3 * k + 1] - cm[1], com[3 * k + 2] - cm[2]};
+                q[0] += Q[6 * k + 0] + M[k] * d[0] * d[0];
+                q[1] += Q[6 * k + 1] + M[k] * d[1] * d[1];
+                q[2] += Q[6 * k + 2] + M[k] * d[2] * d[2];
+                q[3] += Q[6 * k + 3] + M[k] * d[0] * d[1];
+                q[4] += Q[6 * k + 4] + M[k] * d[0] * d[2];
+                q[5] += Q[6 * k + 5] + M[k] * d[1] * d[2];
+            }
+        }
+        M[c] = mm;
+        for (int a = 0; a < 3; ++a) com[3 * c + a] = cm[a];
+        for (int k = 0; k < 6; ++k) Q[6 * c + k] = q[k];
+    }
+}
+
+/* Force with frozen decisions at FP64 positions x[n][3] (sorted order) and
+ * masses m[n].  M, com, Q are caller scratch of ncell entries. */
+void orc_replay(int64_t ng, const int64_t *gbeg, const int64_t *gcnt, int64_t ncell,
+                const int64_t *begin, const int64_t *count, const int64_t *child0,
+                const int32_t *nchild, const int64_t *pc_off, const int64_t *pc,
+                const int64_t *lf_off, const int64_t *lf, const double *x, const double *m,
+                double eps, double *M, double *com, double *Q, double *acc, double *pot) {
+    moments64(ncell, begin, count, child0, nchild, x, m, M, com, Q);
+    double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t g = 0; g < ng; ++g) {
+        for (int64_t i = gbeg[g]; i < gbeg[g] + gcnt[g]; ++i) {
+            double a[3] = {0, 0, 0}, p = 0.0;
+            for (int64_t k = pc_off[g]; k < pc_off[g + 1]; ++k) {
+                int64_t c = pc[k];
+                interact(&x[3 * i], &com[3 * c], M[c], &Q[6 * c], eps2, a, &p, 1);
+            }
+            for (int64_t k = lf_off[g]; k < lf_off[g + 1]; ++k) {
+                int64_t c = lf[k];
+                for (int64_t j = begin[c]; j < begin[c] + count[c]; ++j)
+                    interact(&x[3 * i], &x[3 * j], m[j], NULL, eps2, a, &p, j != i);
+            }
+            for (int a3 = 0; a3 < 3; ++a3) acc[3 * i + a3] = a[a3];
+            pot[i] = p;
+        }
+    }
+}
+
+/* Adjoint of one particle-cell term F(d; M, Q) of Eq. (2), d = com - x_i:
+ * given the cotangent u of the acceleration, returns w = J^T u with
+ * J = dF/dd, and the cotangents of M (gM) and of the six stored Q entries
+ * (gQ: xx, yy, zz, xy, xz, yz).  Point masses: q == NULL. */
+static void term_vjp(const double *d, double mj, const double *q, double eps2, const double *u,
+                     double *w, double *gM, double *gQ) {
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + eps2;
+    if (r2 == 0.0) {
+        w[0] = w[1] = w[2] = 0.0;
+        *gM = 0.0;
+        if (gQ)
+            for (int k = 0; k < 6; ++k) gQ[k] = 0.0;
+        return;
+    }
+    double ri = 1.0 / sqrt(r2), ri2 = ri * ri;
+    double r3 = ri * ri2, r5 = r3 * ri2, r7 = r5 * ri2, r9 = r7 * ri2;
+    double ud = u[0] * d[0] + u[1] * d[1] + u[2] * d[2];
+    /* monopole: F = M d r^-3;  J = M (I r^-3 - 3 d d^T r^-5) */
+    for (int a = 0; a < 3; ++a) w[a] = mj * (u[a] * r3 - 3.0 * d[a] * ud * r5);
+    *gM = ud * r3;
+    if (!q) return;
+    double Qm[3][3] = {{q[0], q[3], q[4]}, {q[3], q[1], q[5]}, {q[4], q[5], q[2]}};
+    double tr = q[0] + q[1] + q[2];
+    double qd[3], qu[3];
+    for (int a = 0; a < 3; ++a) {
+        qd[a] = Qm[a][0] * d[0] + Qm[a][1] * d[1] + Qm[a][2] * d[2];
+        qu[a] = Qm[a][0] * u[0] + Qm[a][1] * u[1] + Qm[a][2] * u[2];
+    }
+    double dqd = d[0] * qd[0] + d[1] * qd[1] + d[2] * qd[2];
+    double uqd = u[0] * qd[0] + u[1] * qd[1] + u[2] * qd[2];
+    /* F = -3/2 tr d r^-5 - 3 Q d r^-5 + 15/2 (d^T Q d) d r^-7
+     * dF_a/dd_b:
+     *   -3/2 tr (delta_ab r^-5 - 5 d_a d_b r^-7)
+     *   -3 (Q_ab r^-5 - 5 (Qd)_a d_b r^-7)
+     *   +15/2 (2 (Qd)_b d_a r^-7 + dqd delta_ab r^-7 - 7 dqd d_a d_b r^-9)
+     * w_b = sum_a u_a dF_a/dd_b */
+    for (int b = 0; b < 3; ++b) {
+        double t = 0.0;
+        t += -1.5 * tr * (u[b] * r5 - 5.0 * ud * d[b] * r7);
+        t += -3.0 * (qu[b] * r5 - 5.0 * uqd * d[b] * r7);
+        t += 7.5 * (2.0 * ud * qd[b] * r7 + dqd * u[b] * r7 - 7.0 * dqd * ud * d[b] * r9);
+        w[b] += t;
+    }
+    /* dF/dQ_ab for the symmetric matrix, per stored entry:
+     *   from -3/2 tr d r^-5: diagonal entries give -3/2 d r^-5
+     *   from -3 Q d r^-5:    entry (a,b) gives -3 r^-5 (e_a d_b + e_b d_a) for a != b,
+     *                        -3 r^-5 e_a d_a for a == b
+     *   from 15/2 dQd d r^-7: entry gives 15/2 r^-7 d (d_a d_b (2 if a != b)) */
+    static const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+    for (int k = 0; k < 6; ++k) {
+        int a = ia[k], b = ib[k];
+        double g = 0.0;
+        if (a == b) {
+            g += -1.5 * ud * r5;
+            g += -3.0 * r5 * u[a] * d[a];
+            g += 7.5 * r7 * ud * d[a] * d[a];
+        } else {
+            g += -3.0 * r5 * (u[a] * d[b] + u[b] * d[a]);
+            g += 7.5 * r7 * ud * 2.0 * d[a] * d[b];
+        }
+        gQ[k] = g;
+    }
+}
+
+/* Adjoint of orc_replay's accelerations: given u[n][3] (sorted order),
+ * accumulate gx[n][3] += u^T da/dx and gm[n] += u^T da/dm.  Cell adjoints
+ * (lM, lcom[3], lQ[6] per cell) are caller scratch; moments must hold the
+ * replay's moments for (x, m).  Source terms are reduced serially. */
+void orc_replay_vjp(int64_t ng, const int64_t *gbeg, const int64_t *gcnt, int64_t ncell,
+                    const int64_t *begin, const int64_t *count, const int64_t *child0,
+                    const int32_t *nchild, const int64_t *pc_off, const int64_t *pc,
+                    const int64_t *lf_off, const int64_t *lf, const double *x, const double *m,
+                    double eps, const double *M, const double *com, const double *Q,
+                    const double *u, double *lM, double *lcom, double *lQ, double *gx,
+                    double *gm) {
+    (void)child0;
+    double eps2 = eps * eps;
+    for (int64_t c = 0; c < ncell; ++c) {
+        lM[c] = 0.0;
+        for (int a = 0; a < 3; ++a) lcom[3 * c + a] = 0.0;
+        for (int k = 0; k < 6; ++k) lQ[6 * c + k] = 0.0;
+    }
+    for (int64_t g = 0; g < ng; ++g) {
+        for (int64_t i = gbeg[g]; i < gbeg[g] + gcnt[g]; ++i) {
+            const double *ui = &u[3 * i];
+            for (int64_t k = pc_off[g]; k < pc_off[g + 1]; ++k) {
+                int64_t c = pc[k];
+                double d[3] = {com[3 * c] - x[3 * i], com[3 * c + 1] - x[3 * i + 1],
+                               com[3 * c + 2] - x[3 * i + 2]};
+                double w[3], gM, gQ[6];
+                term_vjp(d, M[c], &Q[6 * c], eps2, ui, w, &gM, gQ);
+                for (int a = 0; a < 3; ++a) {
+                    gx[3 * i + a] -= w[a];
+                    lcom[3 * c + a] += w[a];
+                }
+                lM[c] += gM;
+                for (int q = 0; q < 6; ++q) lQ[6 * c + q] += gQ[q];
+            }
+            for (int64_t k = lf_off[g]; k < lf_off[g + 1]; ++k) {
+                int64_t c = lf[k];
+                for (int64_t j = begin[c]; j < begin[c] + count[c]; ++j) {
+                    if (j == i) continue;
+                    double d[3] = {x[3 * j] - x[3 * i], x[3 * j + 1] - x[3 * i + 1],
+                                   x[3 * j + 2] - x[3 * i + 2]};
+                    double w[3], gM;
+                    term_vjp(d, m[j], NULL, eps2, ui, w, &gM, NULL);
+                    for (int a = 0; a < 3; ++a) {
+                        gx[3 * i + a] -= w[a];
+                        gx[3 * j + a] += w[a];
+                    }
+                    gm[j] += gM;
+                }
+            }
+        }
+    }
+    /* moments: each particle receives the adjoints of every cell holding it
+     * (its ancestors), with s = x_k - com_c:
+     *   d com / d x_k = m_k / M;  d com / d m_k = s / M;  d M / d m_k = 1;
+     *   d Q / d x_k = m_k (e s^T + s e^T) (the com dependence cancels since
+     *   sum m s = 0);  d Q / d m_k = s s^T. */
+    for (int64_t c = 0; c < ncell; ++c) {
+        if (lM[c] == 0.0 && lcom[3 * c] == 0.0 && lcom[3 * c + 1] == 0.0 &&
+            lcom[3 * c + 2] == 0.0) {
+            int any = 0;
+            for (int q = 0; q < 6; ++q) any |= lQ[6 * c + q] != 0.0;
+            if (!any) continue;
+        }
+        const double *lq = &lQ[6 * c];
+        for (int64_t k = begin[c]; k < begin[c] + count[c]; ++k) {
+            double s[3] = {x[3 * k] - com[3 * c], x[3 * k + 1] - com[3 * c + 1],
+                           x[3 * k + 2] - com[3 * c + 2]};
+            double Ls[3] = {2.0 * lq[0] * s[0] + lq[3] * s[1] + lq[4] * s[2],
+                            lq[3] * s[0] + 2.0 * lq[1] * s[1] + lq[5] * s[2],
+                            lq[4] * s[0] + lq[5] * s[1] + 2.0 * lq[2] * s[2]};
+            for (int a = 0; a < 3; ++a)
+                gx[3 * k + a] += m[k] / M[c] * lcom[3 * c + a] + m[k] * Ls[a];
+            double sLs = lq[0] * s[0] * s[0] + lq[1] * s[1] * s[1] + lq[2] * s[2] * s[2] +
+                         lq[3] * s[0] * s[1] + lq[4] * s[0] * s[2] + lq[5] * s[1] * s[2];
+            gm[k] += lM[c] + (lcom[3 * c] * s[0] + lcom[3 * c + 1] * s[1] +
+                              lcom[3 * c + 2] * s[2]) / M[c] + sLs;
+        }
+    }
+}
