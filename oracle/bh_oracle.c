@@ -636,6 +636,7 @@ void orc_replay_vjp(int64_t ng, const int64_t *gbeg, const int64_t *gcnt, int64_
                     const double *u, double *lM, double *lcom, double *lQ, double *gx,
                     double *gm) {
     (void)child0;
+    (void)nchild;
     double eps2 = eps * eps;
     for (int64_t c = 0; c < ncell; ++c) {
         lM[c] = 0.0;

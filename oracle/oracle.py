@@ -328,3 +328,86 @@ def rel_err(a, ref):
     if a.ndim == 1:
         return np.abs(a - ref) / np.abs(ref)
     return np.sqrt(((a - ref) ** 2).sum(1)) / np.sqrt((ref ** 2).sum(1))
+
+
+# --- differentiation with frozen decisions ------------------------------------
+
+def _declare_adjoint(L):
+    if getattr(L, "_adjoint_declared", False):
+        return
+    L.orc_walk_record.argtypes = [_i64, _i64p, _i64p, _f32p, _f32p, _i64, _i64p, _i32p, _f32p,
+                                  _f32p, _i64p, ctypes.c_void_p, _i64p, ctypes.c_void_p]
+    L.orc_replay.argtypes = [_i64, _i64p, _i64p, _i64, _i64p, _i64p, _i64p, _i32p, _i64p, _i64p,
+                             _i64p, _i64p, _f64p, _f64p, ctypes.c_double, _f64p, _f64p, _f64p,
+                             _f64p, _f64p]
+    L.orc_replay_vjp.argtypes = [_i64, _i64p, _i64p, _i64, _i64p, _i64p, _i64p, _i32p, _i64p,
+                                 _i64p, _i64p, _i64p, _f64p, _f64p, ctypes.c_double, _f64p, _f64p,
+                                 _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
+    L._adjoint_declared = True
+
+
+@dataclass
+class Decisions:
+    """The walk's decisions for every group, held fixed for differentiation:
+    accepted cells pc[pc_off[g]:pc_off[g+1]] and opened leaves
+    lf[lf_off[g]:lf_off[g+1]], on the tree's topology."""
+    tree: Tree
+    pc_off: np.ndarray
+    pc: np.ndarray
+    lf_off: np.ndarray
+    lf: np.ndarray
+
+
+def record_decisions(tree: Tree, theta: float) -> Decisions:
+    L = lib()
+    _declare_adjoint(L)
+    c = tree.cells
+    ng = tree.ngroups
+    ro2 = open_radius2(tree.mom["lf"], tree.mom["deltaf"], theta)
+    args = (ng, tree.gbeg, tree.gcnt, _f32(tree.gc.reshape(-1)), _f32(tree.gh.reshape(-1)),
+            c["ncell"], c["child0"], c["nchild"], _f32(tree.mom["comf"].reshape(-1)), ro2)
+    pc_off = np.zeros(ng + 1, np.int64)
+    lf_off = np.zeros(ng + 1, np.int64)
+    L.orc_walk_record(*args, pc_off, None, lf_off, None)
+    pc = np.zeros(max(int(pc_off[-1]), 1), np.int64)
+    lf = np.zeros(max(int(lf_off[-1]), 1), np.int64)
+    L.orc_walk_record(*args, pc_off, pc.ctypes.data_as(ctypes.c_void_p), lf_off,
+                      lf.ctypes.data_as(ctypes.c_void_p))
+    return Decisions(tree, pc_off, pc, lf_off, lf)
+
+
+def _topo(d: Decisions):
+    t = d.tree
+    c = t.cells
+    return (t.ngroups, t.gbeg, t.gcnt, c["ncell"], c["begin"], c["count"], c["child0"],
+            c["nchild"], d.pc_off, d.pc, d.lf_off, d.lf)
+
+
+def replay(d: Decisions, x_sorted, m_sorted, eps):
+    """Force with frozen decisions at FP64 positions/masses in sorted order.
+    Returns (acc[N,3], pot[N], M, com, Q) in sorted order."""
+    L = lib()
+    _declare_adjoint(L)
+    nc = d.tree.cells["ncell"]
+    n = d.tree.n
+    M, com, Q = np.empty(nc), np.empty(3 * nc), np.empty(6 * nc)
+    acc, pot = np.empty(3 * n), np.empty(n)
+    L.orc_replay(*_topo(d), _f64(x_sorted).reshape(-1), _f64(m_sorted), float(eps), M, com, Q,
+                 acc, pot)
+    return acc.reshape(n, 3), pot, M, com, Q
+
+
+def replay_vjp(d: Decisions, x_sorted, m_sorted, eps, u_sorted):
+    """u^T d(acc)/d(x, m) for the frozen-decision force (sorted order)."""
+    L = lib()
+    _declare_adjoint(L)
+    x = _f64(x_sorted).reshape(-1)
+    m = _f64(m_sorted)
+    _, _, M, com, Q = replay(d, x_sorted, m_sorted, eps)
+    nc = d.tree.cells["ncell"]
+    n = d.tree.n
+    lM, lcom, lQ = np.empty(nc), np.empty(3 * nc), np.empty(6 * nc)
+    gx, gm = np.zeros(3 * n), np.zeros(n)
+    L.orc_replay_vjp(*_topo(d), x, m, float(eps), M, com, Q, _f64(u_sorted).reshape(-1), lM, lcom,
+                     lQ, gx, gm)
+    return gx.reshape(n, 3), gm

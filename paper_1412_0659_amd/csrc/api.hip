@@ -3,6 +3,7 @@
 // array export.  Declarations and contracts are in include/bh.h.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -46,12 +47,12 @@ void free_all(bh_ctx *c) {
         f(s.x); f(s.y); f(s.z); f(s.m); f(s.vx); f(s.vy); f(s.vz); f(s.cid);
         f(c->sort.key[k]); f(c->sort.idx[k]);
     }
-    f(c->acc); f(c->box); f(c->box_part); f(c->status); f(c->work); f(c->totals);
+    f(c->acc); f(c->xyzm); f(c->spill); f(c->box); f(c->box_part); f(c->status); f(c->work); f(c->totals);
     f(c->sort.counts); f(c->sort.scan_part);
     Cells &q = c->cells;
     f(q.prefix); f(q.level); f(q.begin); f(q.count); f(q.child0); f(q.nchild); f(q.parent);
-    f(q.ls); f(q.part); f(q.M); f(q.S); f(q.com); f(q.Q); f(q.wA); f(q.wM); f(q.wQ); f(q.wN);
-    f(q.size); f(q.trm);
+    f(q.ls); f(q.part); f(q.M); f(q.S); f(q.com); f(q.Q); f(q.wA); f(q.wN); f(q.P0); f(q.P1);
+    f(q.P2); f(q.size);
     Groups &g = c->groups;
     f(g.flag); f(g.scan); f(g.begin); f(g.count_dev); f(g.box); f(g.npp); f(g.npc);
     for (auto &e : c->ev)
@@ -72,17 +73,17 @@ int check_status(bh_ctx *c) {
 }
 
 void rebuild(bh_ctx *c, uint32_t n, hipStream_t s) {
-    hipEventRecord(c->ev[0], s);
+    (void)hipEventRecord(c->ev[0], s);
     launch_bbox(c, c->st[c->cur], n, s);
     launch_keys(c, c->st[c->cur], n, s);
     launch_radix_sort(c, n, s);
     launch_gather(c, n, s);
-    hipEventRecord(c->ev[1], s);
+    (void)hipEventRecord(c->ev[1], s);
     launch_build(c, n, s);
     launch_groups(c, n, s);
-    hipEventRecord(c->ev[2], s);
+    (void)hipEventRecord(c->ev[2], s);
     launch_moments(c, s);
-    hipEventRecord(c->ev[3], s);
+    (void)hipEventRecord(c->ev[3], s);
     c->ev_rec[0] = c->ev_rec[1] = c->ev_rec[2] = c->ev_rec[3] = true;
     c->built = true;
     c->have_acc = false;
@@ -168,7 +169,15 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
     c->sort.scan_part_len = std::max(scan_part_len(c->sort.counts_len), scan_part_len(n_max));
     Cells &q = c->cells;
     Groups &g = c->groups;
-    ok = ok && dalloc(&c->acc, n, err) && dalloc(&c->box, 8, err) &&
+    c->walk_grid = std::max(1, c->cus) * walk_blocks_per_cu();
+    {
+        // test hook: a smaller LDS window of the walk stack, so that tests
+        // reach the spill / refill path with moderate trees
+        const char *v = std::getenv("BH_WALK_SMALL_STACK");
+        c->walk_small_stack = v && v[0] == '1';
+    }
+    ok = ok && dalloc(&c->acc, n, err) && dalloc(&c->xyzm, n, err) &&
+         dalloc(&c->spill, (size_t)c->walk_grid * kStackMax, err) && dalloc(&c->box, 8, err) &&
          dalloc(&c->box_part, 6 * 1024, err) && dalloc(&c->status, 4, err) &&
          dalloc(&c->work, 8, err) && dalloc(&c->totals, 2, err) &&
          dalloc(&c->sort.counts, (size_t)c->sort.counts_len, err) &&
@@ -178,8 +187,8 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
          dalloc(&q.parent, nc, err) && dalloc(&q.ls, kLsSize, err) &&
          dalloc(&q.part, kGrid + 1, err) && dalloc(&q.M, nc, err) && dalloc(&q.S, 3 * nc, err) &&
          dalloc(&q.com, 3 * nc, err) && dalloc(&q.Q, 6 * nc, err) && dalloc(&q.wA, nc, err) &&
-         dalloc(&q.wM, nc, err) && dalloc(&q.wQ, nc, err) && dalloc(&q.wN, nc, err) &&
-         dalloc(&q.size, nc, err) && dalloc(&q.trm, nc, err) && dalloc(&g.flag, n, err) &&
+         dalloc(&q.wN, nc, err) && dalloc(&q.P0, nc, err) && dalloc(&q.P1, nc, err) &&
+         dalloc(&q.P2, nc, err) && dalloc(&q.size, nc, err) && dalloc(&g.flag, n, err) &&
          dalloc(&g.scan, n, err) && dalloc(&g.begin, n + 1, err) &&
          dalloc(&g.count_dev, 1, err) && dalloc(&g.box, 2 * n, err) && dalloc(&g.npp, n, err) &&
          dalloc(&g.npc, n, err);
@@ -191,7 +200,6 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
         delete c;
         return BH_ENOMEM;
     }
-    c->walk_grid = std::max(1, c->cus) * walk_blocks_per_cu();
     *out = c;
     return BH_OK;
 }
@@ -241,13 +249,13 @@ int leapfrog_step(bh_ctx *c, float dt, float theta, float eps, hipStream_t s) {
     if (!valid_eps(eps)) return fail(c, BH_EINVAL, "eps must be finite and >= 0");
     if (!c->built) return fail(c, BH_ESTATE, "leapfrog_step before tree_build");
     uint32_t n = (uint32_t)c->n;
-    hipEventRecord(c->ev[6], s);
+    (void)hipEventRecord(c->ev[6], s);
     if (!c->have_acc || theta != c->acc_theta || eps != c->acc_eps) force(c, theta, eps, s);
     launch_kick_drift(c, 0.5f * dt, dt, n, s);
     rebuild(c, n, s);
     force(c, theta, eps, s);
     launch_kick(c, 0.5f * dt, n, s);
-    hipEventRecord(c->ev[7], s);
+    (void)hipEventRecord(c->ev[7], s);
     c->ev_rec[6] = c->ev_rec[7] = true;
     BH_HIP(c, hipGetLastError());
     return BH_OK;

@@ -19,6 +19,7 @@ constexpr int kLsSize = 24;             // level_start entries (23 used)
 constexpr int kGrid = 1024;             // fixed grid of the level-wise build kernels
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kNone = 0xffffffffu;
+constexpr int kStackMax = 1408;         // walk stack bound: 21 levels x 64 ranges + root
 
 // device status word bits
 constexpr uint32_t kStNonFinite = 1u;
@@ -41,11 +42,11 @@ struct Cells {
     double *M, *S, *com, *Q;  // [c], [c][3], [c][3], [c][6]
     // records read by the walk
     float4 *wA;  // com (FP32) and r_open^2 of the last theta
-    float4 *wM;  // M, Qxx, Qyy, Qzz
-    float4 *wQ;  // Qxy, Qxz, Qyz, trace(Q)/2
     uint2 *wN;   // internal: (child0, nchild); leaf: (begin, count | kLeafBit)
+    float4 *P0;  // particle-cell record: com x, y, z, M
+    float4 *P1;  // -3 Qxx, -3 Qyy, -3 Qzz, -3 Qxy
+    float4 *P2;  // -3 Qxz, -3 Qyz, trace(Q) / 2, -3 trace(Q) / 2
     float2 *size;  // cell size l, |com - geometric centre|
-    float *trm;    // -3/2 trace(Q) per cell (second constant of the expansion)
 };
 
 struct Groups {
@@ -75,6 +76,8 @@ struct bh_ctx {
     bh::State st[2]{};
     int cur = 0;
     float4 *acc = nullptr;  // sorted acceleration + potential
+    float4 *xyzm = nullptr; // sorted position + mass, one record per particle
+    uint32_t *spill = nullptr;  // walk stack spill area, kStackMax per wave
     float *box = nullptr;   // [8]: lo xyz, side, scale
     float *box_part = nullptr;
     uint32_t *status = nullptr;
@@ -87,6 +90,7 @@ struct bh_ctx {
     bool built = false, have_acc = false;
     float acc_theta = 0.f, acc_eps = 0.f;
     int walk_grid = 0;
+    bool walk_small_stack = false;  // test hook: 128-entry LDS stack window
 
     // events: build start, after sort, after octree+groups, after moments,
     // walk start, walk end, step start, step end

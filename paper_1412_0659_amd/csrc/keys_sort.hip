@@ -232,14 +232,16 @@ void launch_radix_sort(bh_ctx *c, uint32_t n, hipStream_t st) {
 // ---- gather the state into sorted order ------------------------------------
 
 __global__ __launch_bounds__(256) void k_gather(const uint32_t *__restrict__ idx, uint32_t n,
-                                                State a, State b, uint32_t *status) {
+                                                State a, State b, float4 *__restrict__ xyzm) {
     uint32_t i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     uint32_t s = idx[i];
-    b.x[i] = a.x[s];
-    b.y[i] = a.y[s];
-    b.z[i] = a.z[s];
-    b.m[i] = a.m[s];
+    float px = a.x[s], py = a.y[s], pz = a.z[s], pm = a.m[s];
+    b.x[i] = px;
+    b.y[i] = py;
+    b.z[i] = pz;
+    b.m[i] = pm;
+    xyzm[i] = make_float4(px, py, pz, pm);
     b.vx[i] = a.vx[s];
     b.vy[i] = a.vy[s];
     b.vz[i] = a.vz[s];
@@ -249,7 +251,7 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t *__restrict__ idx
 void launch_gather(bh_ctx *c, uint32_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_gather, dim3(cdiv(n, 256)), dim3(256), 0, st,
                        (const uint32_t *)c->sort.idx[0], n, c->st[c->cur], c->st[c->cur ^ 1],
-                       c->status);
+                       c->xyzm);
     c->cur ^= 1;
 }
 

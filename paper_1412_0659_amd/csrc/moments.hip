@@ -11,8 +11,10 @@
 // particles in sorted order, a parent over its children in child order),
 // with contraction off, so the result does not depend on the launch.  Leaves
 // first, then internal cells level by level from the deepest.  The walk
-// reads FP32 copies: com, M, Q, and the opening radius
-// r_open = l / theta + |com - geometric centre| (l = cell size).
+// reads FP32 copies: com and the opening radius
+// r_open = l / theta + |com - geometric centre| (l = cell size) for the
+// opening test, and (com, M, -3 Q, tr Q / 2, -3 tr Q / 2) for the
+// particle-cell terms.
 #include "bh_internal.h"
 
 namespace bh {
@@ -116,9 +118,11 @@ __global__ __launch_bounds__(256) void k_moments_final(Cells c, const float *__r
         const double *q = c.Q + 6 * (size_t)i;
         double tr = (q[0] + q[1]) + q[2];
         c.wA[i] = make_float4((float)c0, (float)c1, (float)c2, 0.f);
-        c.wM[i] = make_float4((float)c.M[i], (float)q[0], (float)q[1], (float)q[2]);
-        c.wQ[i] = make_float4((float)q[3], (float)q[4], (float)q[5], (float)(0.5 * tr));
-        c.trm[i] = (float)(-1.5 * tr);
+        c.P0[i] = make_float4((float)c0, (float)c1, (float)c2, (float)c.M[i]);
+        c.P1[i] = make_float4((float)(-3.0 * q[0]), (float)(-3.0 * q[1]), (float)(-3.0 * q[2]),
+                              (float)(-3.0 * q[3]));
+        c.P2[i] = make_float4((float)(-3.0 * q[4]), (float)(-3.0 * q[5]), (float)(0.5 * tr),
+                              (float)(-1.5 * tr));
         uint32_t nch = c.nchild[i];
         c.wN[i] = nch ? make_uint2(c.child0[i], nch) : make_uint2(c.begin[i], c.count[i] | kLeafBit);
         c.size[i] = make_float2((float)lc, (float)dl);

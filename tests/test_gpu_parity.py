@@ -175,3 +175,48 @@ def test_errors_and_state():
     t.build(to_dev(s.pos), to_dev(s.mass))
     t.sync()
     t.close()
+
+
+@pytest.mark.parametrize("n,theta", [(60000, 0.3), (30000, 1e-6)])
+def test_stack_spill_and_refill(oracle, monkeypatch, n, theta):
+    """A dense tree (one particle per leaf) with the walk stack's LDS window
+    cut to 128 entries, so ranges spill to device memory and come back."""
+    monkeypatch.setenv("BH_WALK_SMALL_STACK", "1")
+    rng = np.random.default_rng(21)
+    pos = rng.uniform(-1, 1, (n, 3)).astype(np.float32)
+    m = np.full(n, 1.0 / n, np.float32)
+    print(f"stack spill case n={n} theta={theta}", flush=True)
+    t = gpu_tree(pos, m, nleaf=1, ncrit=64)
+    acc, pot = gpu_force(t, theta, 1e-3)
+    ot = oracle.build_tree(pos, m, 1, 64)
+    oacc, opot, onpp, onpc = oracle.walk(ot, theta, 1e-3)
+    assert np.array_equal(t.export("group_npp").astype(np.int64), onpp)
+    assert np.array_equal(t.export("group_npc").astype(np.int64), onpc)
+    ea, ep = rel_err(acc, oacc), rel_err(pot, opot)
+    assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
+    assert np.median(ep) <= MED_TOL and np.percentile(ep, 99) <= P99_TOL
+    t.close()
+
+
+def test_every_group_size(oracle):
+    """Groups of every size 1..64 (one or two evaluation phases): ncrit = 64
+    over clusters of k coincident-free points far apart."""
+    rng = np.random.default_rng(8)
+    blobs = []
+    for k in range(1, 65):
+        centre = rng.uniform(-100, 100, 3)
+        blobs.append(centre + rng.normal(size=(k, 3)) * 1e-3)
+    pos = np.concatenate(blobs).astype(np.float32)
+    m = rng.uniform(0.5, 1.5, pos.shape[0]).astype(np.float32)
+    t = gpu_tree(pos, m)
+    ot = oracle.build_tree(pos, m)
+    assert_tree_equal(t, ot)
+    sizes = set(ot.gcnt.tolist())
+    assert len(sizes) > 30
+    acc, pot = gpu_force(t, 0.5, 1e-4)
+    oacc, opot, onpp, onpc = oracle.walk(ot, 0.5, 1e-4)
+    assert np.array_equal(t.export("group_npp").astype(np.int64), onpp)
+    ea, ep = rel_err(acc, oacc), rel_err(pot, opot)
+    assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
+    assert np.median(ep) <= MED_TOL and np.percentile(ep, 99) <= P99_TOL
+    t.close()
