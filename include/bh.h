@@ -62,9 +62,17 @@ typedef struct bh_params {
     int32_t nleaf;    /* a cell holding more than nleaf particles is split
                          (Sec. I.A uses 16); 1..64 */
     int32_t ncrit;    /* target groups hold at most ncrit particles; 1..64 */
-    int32_t far_fp16; /* reserved, must be 0 */
-    int32_t pos_fp64; /* reserved, must be 0 */
-    int32_t reserved[4];
+    int32_t far_fp16; /* 1: particle-cell (far-field) terms in packed FP16 with
+                         FP32 accumulation, each (group, cell) pair rescaled by
+                         powers of two so FP16 values are of order one; pairs too
+                         close for that range, and all particle-particle terms,
+                         stay FP32.  Same interaction lists as 0 (FP32). */
+    int32_t pos_fp64; /* 1: keep an FP64 master copy of the positions; the
+                         leapfrog drift is done in FP64 and the tree is built
+                         from its FP32 rounding.  0: FP32 positions. */
+    int32_t adjoint;  /* 1: allocate the buffers of tree_force_vjp (FP64 cell and
+                         particle adjoints, 100 bytes per cell + 40 per particle) */
+    int32_t reserved[3];
 } bh_params;
 
 typedef struct bh_ctx bh_ctx;
@@ -109,6 +117,59 @@ int tree_force(bh_ctx *ctx, float theta, float eps, float *acc, float *pot, hipS
  * computed first when the last call did not leave one for (theta, eps).
  * Errors: BH_EINVAL (dt not finite, theta/eps out of range), BH_ESTATE. */
 int leapfrog_step(bh_ctx *ctx, float dt, float theta, float eps, hipStream_t s);
+
+/* Adjoint of tree_force with the walk's decisions held fixed (the opening
+ * decisions, tree topology and group boxes are piecewise constant and have
+ * zero derivative): for the cotangent u of the accelerations,
+ *   g_pos  += coef * u^T d(acc)/d(pos)     (device, [n][3], caller order)
+ *   g_mass += coef * u^T d(acc)/d(mass)    (device, [n], caller order)
+ * either output may be NULL.  The accelerations are those of Sec. VI.A
+ * Eq. (2) over the lists of a walk of the current tree with (theta, eps);
+ * cells enter through their moments (Sec. I.A, Eq. (1)), whose adjoint is
+ * applied to every particle of every cell.  u is device [n][3] caller order.
+ * Source terms are reduced with FP64 atomics, so results may differ in the
+ * last bits between runs.  Errors: BH_EINVAL (bad theta/eps, null u, context
+ * without adjoint = 1), BH_ESTATE (no tree). */
+int tree_force_vjp(bh_ctx *ctx, float theta, float eps, const float *u, float coef,
+                   float *g_pos, float *g_mass, hipStream_t s);
+
+/* Transpose of the leapfrog drift x += dt v for the adjoint sweep:
+ * gv += dt * gx (device, [n][3], caller order). */
+int leapfrog_vjp_drift(bh_ctx *ctx, float dt, const float *gx, float *gv, hipStream_t s);
+
+/* Bytes of a state snapshot for the current n (0 if nothing built). */
+int64_t bh_state_bytes(const bh_ctx *ctx);
+
+/* Snapshot the particle state exactly as held (sorted order, caller
+ * indices, FP64 positions if kept) into device memory dst of
+ * bh_state_bytes() bytes.  Loading it later reproduces the same tree, the
+ * same walk and so bit-identical steps; this is how the adjoint sweep
+ * replays a checkpointed trajectory, and it serves as a restart point. */
+int bh_save_state(bh_ctx *ctx, void *dst, hipStream_t s);
+
+/* Restore a snapshot of n particles (device memory) and rebuild the tree. */
+int bh_load_state(bh_ctx *ctx, const void *src, int64_t n, hipStream_t s);
+
+/* Polar grid of the surface-density observable. */
+typedef struct bh_cic_grid {
+    float r_min, r_max;   /* radial range, 0 <= r_min < r_max */
+    int32_t n_r, n_phi;   /* cells; n_r * n_phi <= 65536 */
+} bh_cic_grid;
+
+/* Face-on surface density of the selected particles (sel: device [n] bytes,
+ * nonzero = selected, NULL = all) on the polar grid, cloud-in-cell in
+ * (R, phi) with phi periodic: cell centres R_i = r_min + (i + 1/2) dR,
+ * phi_j = (j + 1/2) dphi; mass / cell area.  pos device [n][3], mass [n],
+ * density device [n_r][n_phi]. */
+int bh_cic_density(bh_ctx *ctx, const float *pos, const float *mass, const uint8_t *sel,
+                   int64_t n, const bh_cic_grid *grid, float *density, hipStream_t s);
+
+/* Adjoint of bh_cic_density: g_pos += (d density/d pos)^T g_density,
+ * g_mass += (d density/d mass)^T g_density (device, caller order; either may
+ * be NULL). */
+int bh_cic_density_vjp(bh_ctx *ctx, const float *pos, const float *mass, const uint8_t *sel,
+                       int64_t n, const bh_cic_grid *grid, const float *g_density,
+                       float *g_pos, float *g_mass, hipStream_t s);
 
 /* Copy the particle state out in caller order (device pointers, [n][3];
  * either may be NULL).  Synchronises s and reports latched device status. */

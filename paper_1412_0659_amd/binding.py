@@ -43,7 +43,12 @@ class BhError(RuntimeError):
 class bh_params(ctypes.Structure):
     _fields_ = [("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32),
                 ("far_fp16", ctypes.c_int32), ("pos_fp64", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("adjoint", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class bh_cic_grid(ctypes.Structure):
+    _fields_ = [("r_min", ctypes.c_float), ("r_max", ctypes.c_float),
+                ("n_r", ctypes.c_int32), ("n_phi", ctypes.c_int32)]
 
 
 class bh_stats(ctypes.Structure):
@@ -56,7 +61,9 @@ class bh_stats(ctypes.Structure):
 
 SYMBOLS = ["bh_create", "bh_destroy", "tree_build", "bh_set_state", "tree_force",
            "leapfrog_step", "bh_get_state", "bh_sync", "bh_stats_get", "bh_export",
-           "bh_strerror", "bh_last_error"]
+           "bh_strerror", "bh_last_error", "tree_force_vjp", "leapfrog_vjp_drift",
+           "bh_state_bytes", "bh_save_state", "bh_load_state", "bh_cic_density",
+           "bh_cic_density_vjp"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -85,6 +92,15 @@ def load():
         "bh_export": ([_vp, c_int, _vp, i64, ctypes.POINTER(i64), _vp], c_int),
         "bh_strerror": ([c_int], ctypes.c_char_p),
         "bh_last_error": ([_vp], ctypes.c_char_p),
+        "tree_force_vjp": ([_vp, f32, f32, _vp, f32, _vp, _vp, _vp], c_int),
+        "leapfrog_vjp_drift": ([_vp, f32, _vp, _vp, _vp], c_int),
+        "bh_state_bytes": ([_vp], i64),
+        "bh_save_state": ([_vp, _vp, _vp], c_int),
+        "bh_load_state": ([_vp, _vp, i64, _vp], c_int),
+        "bh_cic_density": ([_vp, _vp, _vp, _vp, i64, ctypes.POINTER(bh_cic_grid), _vp, _vp],
+                           c_int),
+        "bh_cic_density_vjp": ([_vp, _vp, _vp, _vp, i64, ctypes.POINTER(bh_cic_grid), _vp, _vp,
+                                _vp, _vp], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -121,8 +137,9 @@ def _stream(stream=None):
 
 # --- the C entry points, same names ------------------------------------------
 
-def bh_create(n_max: int, nleaf: int = 16, ncrit: int = 64):
-    p = bh_params(nleaf, ncrit, 0, 0)
+def bh_create(n_max: int, nleaf: int = 16, ncrit: int = 64, far_fp16: bool = False,
+              pos_fp64: bool = False, adjoint: bool = False):
+    p = bh_params(nleaf, ncrit, int(bool(far_fp16)), int(bool(pos_fp64)), int(bool(adjoint)))
     out = _vp()
     rc = load().bh_create(ctypes.byref(out), int(n_max), ctypes.byref(p))
     _check(None, rc)
@@ -181,12 +198,78 @@ def bh_export(ctx, name: str, count: int, stream=None) -> np.ndarray:
     return out.reshape(-1, width) if width > 1 else out
 
 
+def _u8ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()
+            and t.dtype in (torch.uint8, torch.bool)):
+        raise TypeError("expected a contiguous uint8/bool CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def tree_force_vjp(ctx, theta, eps, u, coef, g_pos=None, g_mass=None, stream=None):
+    _check(ctx, load().tree_force_vjp(ctx, float(theta), float(eps), _ptr(u), float(coef),
+                                      _ptr(g_pos), _ptr(g_mass), _stream(stream)))
+
+
+def leapfrog_vjp_drift(ctx, dt, gx, gv, stream=None):
+    _check(ctx, load().leapfrog_vjp_drift(ctx, float(dt), _ptr(gx), _ptr(gv), _stream(stream)))
+
+
+def bh_state_bytes(ctx) -> int:
+    return int(load().bh_state_bytes(ctx))
+
+
+def bh_save_state(ctx, dst, stream=None):
+    import torch
+    if not (isinstance(dst, torch.Tensor) and dst.is_cuda and dst.is_contiguous()
+            and dst.dtype == torch.uint8 and dst.numel() >= bh_state_bytes(ctx)):
+        raise TypeError("expected a large enough contiguous uint8 CUDA tensor")
+    _check(ctx, load().bh_save_state(ctx, ctypes.c_void_p(dst.data_ptr()), _stream(stream)))
+
+
+def bh_load_state(ctx, src, n, stream=None):
+    _check(ctx, load().bh_load_state(ctx, ctypes.c_void_p(src.data_ptr()), int(n),
+                                     _stream(stream)))
+
+
+def bh_cic_density(ctx, pos, mass, sel, grid, density, stream=None):
+    g = bh_cic_grid(*grid)
+    _check(ctx, load().bh_cic_density(ctx, _ptr(pos), _ptr(mass), _u8ptr(sel), mass.shape[0],
+                                      ctypes.byref(g), _ptr(density), _stream(stream)))
+
+
+def bh_cic_density_vjp(ctx, pos, mass, sel, grid, g_density, g_pos=None, g_mass=None,
+                       stream=None):
+    g = bh_cic_grid(*grid)
+    _check(ctx, load().bh_cic_density_vjp(ctx, _ptr(pos), _ptr(mass), _u8ptr(sel), mass.shape[0],
+                                          ctypes.byref(g), _ptr(g_density), _ptr(g_pos),
+                                          _ptr(g_mass), _stream(stream)))
+
+
 class Tree:
     """Owns one library context; methods call the C entry points."""
 
-    def __init__(self, n_max: int, nleaf: int = 16, ncrit: int = 64):
-        self.ctx = bh_create(n_max, nleaf, ncrit)
+    def __init__(self, n_max: int, nleaf: int = 16, ncrit: int = 64, far_fp16: bool = False,
+                 pos_fp64: bool = False, adjoint: bool = False):
+        self.ctx = bh_create(n_max, nleaf, ncrit, far_fp16, pos_fp64, adjoint)
         self.n = 0
+
+    def save(self):
+        """Exact snapshot of the state (device bytes)."""
+        import torch
+        buf = torch.empty(bh_state_bytes(self.ctx), dtype=torch.uint8, device="cuda")
+        bh_save_state(self.ctx, buf)
+        return buf
+
+    def restore(self, buf, n=None):
+        bh_load_state(self.ctx, buf, self.n if n is None else n)
+        if n is not None:
+            self.n = n
+
+    def force_vjp(self, theta, eps, u, coef=1.0, g_pos=None, g_mass=None):
+        tree_force_vjp(self.ctx, theta, eps, u, coef, g_pos, g_mass)
 
     def close(self):
         if self.ctx:

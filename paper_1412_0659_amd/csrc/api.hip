@@ -45,6 +45,7 @@ void free_all(bh_ctx *c) {
     for (int k = 0; k < 2; ++k) {
         State &s = c->st[k];
         f(s.x); f(s.y); f(s.z); f(s.m); f(s.vx); f(s.vy); f(s.vz); f(s.cid);
+        f(s.x64); f(s.y64); f(s.z64);
         f(c->sort.key[k]); f(c->sort.idx[k]);
     }
     f(c->acc); f(c->xyzm); f(c->spill); f(c->box); f(c->box_part); f(c->status); f(c->work); f(c->totals);
@@ -55,6 +56,7 @@ void free_all(bh_ctx *c) {
     f(q.P2); f(q.size);
     Groups &g = c->groups;
     f(g.flag); f(g.scan); f(g.begin); f(g.count_dev); f(g.box); f(g.npp); f(g.npc);
+    f(c->lcell); f(c->gsrc); f(c->usort); f(c->leafof); f(c->cic);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
 }
@@ -132,7 +134,8 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
     prm.ncrit = 64;
     if (p) prm = *p;
     if (n_max <= 0 || prm.nleaf < 1 || prm.nleaf > 64 || prm.ncrit < 1 || prm.ncrit > 64 ||
-        prm.far_fp16 != 0 || prm.pos_fp64 != 0)
+        prm.far_fp16 < 0 || prm.far_fp16 > 1 || prm.pos_fp64 < 0 || prm.pos_fp64 > 1 ||
+        prm.adjoint < 0 || prm.adjoint > 1)
         return BH_EINVAL;
     // cells: <= n leaves + 21 levels x n / (nleaf + 1) internal cells; the walk
     // packs a cell index into 29 bits
@@ -164,6 +167,8 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
              dalloc(&s.m, n, err) && dalloc(&s.vx, n, err) && dalloc(&s.vy, n, err) &&
              dalloc(&s.vz, n, err) && dalloc(&s.cid, n, err) && dalloc(&c->sort.key[k], n, err) &&
              dalloc(&c->sort.idx[k], n, err);
+        if (ok && prm.pos_fp64)
+            ok = dalloc(&s.x64, n, err) && dalloc(&s.y64, n, err) && dalloc(&s.z64, n, err);
     }
     c->sort.counts_len = sort_counts_len(n_max);
     c->sort.scan_part_len = std::max(scan_part_len(c->sort.counts_len), scan_part_len(n_max));
@@ -191,7 +196,10 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
          dalloc(&q.P2, nc, err) && dalloc(&q.size, nc, err) && dalloc(&g.flag, n, err) &&
          dalloc(&g.scan, n, err) && dalloc(&g.begin, n + 1, err) &&
          dalloc(&g.count_dev, 1, err) && dalloc(&g.box, 2 * n, err) && dalloc(&g.npp, n, err) &&
-         dalloc(&g.npc, n, err);
+         dalloc(&g.npc, n, err) && dalloc(&c->cic, 65536, err);
+    if (ok && prm.adjoint)
+        ok = dalloc(&c->lcell, 10 * nc, err) && dalloc(&c->gsrc, 4 * n, err) &&
+             dalloc(&c->usort, n, err) && dalloc(&c->leafof, n, err);
     for (auto &e : c->ev)
         if (ok && hipEventCreate(&e) != hipSuccess) ok = false;
     if (ok && hipMemset(c->status, 0, 4 * sizeof(uint32_t)) != hipSuccess) ok = false;
@@ -377,6 +385,123 @@ int bh_export(bh_ctx *c, int array, void *dst, int64_t cap_bytes, int64_t *nbyte
     if (bytes) BH_HIP(c, hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
     if (nbytes) *nbytes = (int64_t)bytes;
     return check_status(c);
+}
+
+int tree_force_vjp(bh_ctx *c, float theta, float eps, const float *u, float coef,
+                   float *g_pos, float *g_mass, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!valid_theta(theta)) return fail(c, BH_EINVAL, "theta must be in (0, 1]");
+    if (!valid_eps(eps)) return fail(c, BH_EINVAL, "eps must be finite and >= 0");
+    if (!u || !std::isfinite(coef)) return fail(c, BH_EINVAL, "null cotangent or bad coef");
+    if (!c->p.adjoint) return fail(c, BH_EINVAL, "context created without adjoint = 1");
+    if (!c->built) return fail(c, BH_ESTATE, "tree_force_vjp before tree_build");
+    if (!g_pos && !g_mass) return BH_OK;
+    launch_walk_prep(c, theta, s);
+    launch_walk_vjp(c, eps, u, coef, g_pos, g_mass, s);
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+int leapfrog_vjp_drift(bh_ctx *c, float dt, const float *gx, float *gv, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!gx || !gv || !std::isfinite(dt)) return fail(c, BH_EINVAL, "bad arguments");
+    if (!c->built) return fail(c, BH_ESTATE, "no state");
+    launch_axpy3(gx, gv, dt, (uint32_t)c->n, s);
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+int64_t bh_state_bytes(const bh_ctx *c) {
+    if (!c || !c->built) return 0;
+    return c->n * (int64_t)(7 * sizeof(float) + sizeof(uint32_t) +
+                            (c->p.pos_fp64 ? 3 * sizeof(double) : 0));
+}
+
+int bh_save_state(bh_ctx *c, void *dst, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!dst) return fail(c, BH_EINVAL, "null destination");
+    if (!c->built) return fail(c, BH_ESTATE, "no state");
+    const size_t n = (size_t)c->n;
+    const State &st = c->st[c->cur];
+    char *p = static_cast<char *>(dst);
+    float *const fa[7] = {st.x, st.y, st.z, st.m, st.vx, st.vy, st.vz};
+    for (float *f : fa) {
+        BH_HIP(c, hipMemcpyAsync(p, f, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+        p += n * sizeof(float);
+    }
+    BH_HIP(c, hipMemcpyAsync(p, st.cid, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    p += n * sizeof(uint32_t);
+    if (c->p.pos_fp64) {
+        double *const da[3] = {st.x64, st.y64, st.z64};
+        for (double *d : da) {
+            BH_HIP(c, hipMemcpyAsync(p, d, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            p += n * sizeof(double);
+        }
+    }
+    return BH_OK;
+}
+
+int bh_load_state(bh_ctx *c, const void *src, int64_t n64, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!src) return fail(c, BH_EINVAL, "null source");
+    int rc = check_n(c, n64);
+    if (rc) return rc;
+    const size_t n = (size_t)n64;
+    c->n = n64;
+    State &st = c->st[c->cur];
+    const char *p = static_cast<const char *>(src);
+    float *const fa[7] = {st.x, st.y, st.z, st.m, st.vx, st.vy, st.vz};
+    for (float *f : fa) {
+        BH_HIP(c, hipMemcpyAsync(f, p, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+        p += n * sizeof(float);
+    }
+    BH_HIP(c, hipMemcpyAsync(st.cid, p, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    p += n * sizeof(uint32_t);
+    if (c->p.pos_fp64) {
+        double *const da[3] = {st.x64, st.y64, st.z64};
+        for (double *d : da) {
+            BH_HIP(c, hipMemcpyAsync(d, p, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            p += n * sizeof(double);
+        }
+    }
+    rebuild(c, (uint32_t)n, s);
+    c->ev_rec[6] = c->ev_rec[7] = false;
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+static int check_grid(bh_ctx *c, const bh_cic_grid *g) {
+    if (!g || !(g->r_min >= 0.f) || !(g->r_max > g->r_min) || !std::isfinite(g->r_max) ||
+        g->n_r < 1 || g->n_phi < 1 || (int64_t)g->n_r * g->n_phi > 65536)
+        return fail(c, BH_EINVAL, "bad surface-density grid");
+    return BH_OK;
+}
+
+int bh_cic_density(bh_ctx *c, const float *pos, const float *mass, const uint8_t *sel,
+                   int64_t n, const bh_cic_grid *grid, float *density, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    int rc = check_grid(c, grid);
+    if (rc) return rc;
+    if (!pos || !mass || !density || n < 0 || n > c->nmax)
+        return fail(c, BH_EINVAL, "bad arguments");
+    launch_cic(pos, mass, sel, (uint32_t)n, grid->r_min, grid->r_max, grid->n_r, grid->n_phi,
+               c->cic, density, s);
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+int bh_cic_density_vjp(bh_ctx *c, const float *pos, const float *mass, const uint8_t *sel,
+                       int64_t n, const bh_cic_grid *grid, const float *g_density,
+                       float *g_pos, float *g_mass, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    int rc = check_grid(c, grid);
+    if (rc) return rc;
+    if (!pos || !mass || !g_density || n < 0 || n > c->nmax)
+        return fail(c, BH_EINVAL, "bad arguments");
+    launch_cic_vjp(pos, mass, sel, (uint32_t)n, grid->r_min, grid->r_max, grid->n_r, grid->n_phi,
+                   g_density, g_pos, g_mass, s);
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
 }
 
 }  // extern "C"

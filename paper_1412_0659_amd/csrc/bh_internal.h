@@ -30,6 +30,7 @@ constexpr uint32_t kStOverflow = 4u;
 struct State {
     float *x, *y, *z, *m, *vx, *vy, *vz;
     uint32_t *cid;  // caller index of each sorted slot
+    double *x64, *y64, *z64;  // FP64 master positions (pos_fp64 contexts), else null
 };
 
 // Octree cells, breadth-first order (level, then key).
@@ -87,6 +88,13 @@ struct bh_ctx {
     bh::Cells cells{};
     bh::Groups groups{};
 
+    // adjoint buffers (contexts created with adjoint = 1)
+    double *lcell = nullptr;   // [cells][10]: dL/dM, dL/dcom xyz, dL/dQ xx yy zz xy xz yz
+    double *gsrc = nullptr;    // [n][4]: dL/dx xyz, dL/dm of sorted particles
+    float4 *usort = nullptr;   // [n] cotangent of the accelerations, sorted order
+    uint32_t *leafof = nullptr;  // [n] leaf cell of each sorted particle
+    double *cic = nullptr;       // [65536] accumulator of the surface-density grid
+
     bool built = false, have_acc = false;
     float acc_theta = 0.f, acc_eps = 0.f;
     int walk_grid = 0;
@@ -100,6 +108,19 @@ struct bh_ctx {
 };
 
 namespace bh {
+
+// walk_vjp.hip: coef * u^T d(acc)/d(x, m) accumulated into caller-order
+// g_pos [n][3] / g_mass [n] (either may be null); u is caller order [n][3]
+void launch_walk_vjp(bh_ctx *c, float eps, const float *u, float coef, float *g_pos,
+                     float *g_mass, hipStream_t st);
+void launch_axpy3(const float *x, float *y, float a, uint32_t n, hipStream_t st);
+
+// loss.hip: cloud-in-cell surface density on a polar grid and its adjoint
+void launch_cic(const float *pos, const float *mass, const uint8_t *sel, uint32_t n, float rmin,
+                float rmax, int nr, int nphi, double *scratch, float *density, hipStream_t st);
+void launch_cic_vjp(const float *pos, const float *mass, const uint8_t *sel, uint32_t n,
+                    float rmin, float rmax, int nr, int nphi, const float *gden, float *g_pos,
+                    float *g_mass, hipStream_t st);
 
 // keys_sort.hip
 void launch_bbox(bh_ctx *c, const State &s, uint32_t n, hipStream_t st);

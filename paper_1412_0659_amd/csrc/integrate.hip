@@ -27,9 +27,15 @@ __global__ __launch_bounds__(256) void k_ingest(const float *__restrict__ pos,
                                                 State s, uint32_t *status) {
     uint32_t i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    s.x[i] = pos[3 * (size_t)i];
-    s.y[i] = pos[3 * (size_t)i + 1];
-    s.z[i] = pos[3 * (size_t)i + 2];
+    const float px = pos[3 * (size_t)i], py = pos[3 * (size_t)i + 1], pz = pos[3 * (size_t)i + 2];
+    s.x[i] = px;
+    s.y[i] = py;
+    s.z[i] = pz;
+    if (s.x64) {
+        s.x64[i] = px;
+        s.y64[i] = py;
+        s.z64[i] = pz;
+    }
     float mi = mass[i];
     s.m[i] = mi;
     if (!(mi > 0.f) || !isfinite(mi)) atomicOr(status, kStMass);
@@ -64,7 +70,8 @@ __global__ __launch_bounds__(256) void k_kick(State s, const float4 *__restrict_
     s.vz[i] = fmaf(a.z, h, s.vz[i]);
 }
 
-// v += a h; x += v dt
+// v += a h; x += v dt.  With an FP64 master copy the drift is done in FP64
+// and the FP32 positions the tree is built from are its rounding.
 __global__ __launch_bounds__(256) void k_kick_drift(State s, const float4 *__restrict__ acc,
                                                     uint32_t n, float h, float dt) {
     uint32_t i = blockIdx.x * 256 + threadIdx.x;
@@ -74,9 +81,21 @@ __global__ __launch_bounds__(256) void k_kick_drift(State s, const float4 *__res
     s.vx[i] = vx;
     s.vy[i] = vy;
     s.vz[i] = vz;
-    s.x[i] = fmaf(vx, dt, s.x[i]);
-    s.y[i] = fmaf(vy, dt, s.y[i]);
-    s.z[i] = fmaf(vz, dt, s.z[i]);
+    if (s.x64) {
+        const double d = dt;
+        const double x = fma((double)vx, d, s.x64[i]), y = fma((double)vy, d, s.y64[i]),
+                     z = fma((double)vz, d, s.z64[i]);
+        s.x64[i] = x;
+        s.y64[i] = y;
+        s.z64[i] = z;
+        s.x[i] = (float)x;
+        s.y[i] = (float)y;
+        s.z[i] = (float)z;
+    } else {
+        s.x[i] = fmaf(vx, dt, s.x[i]);
+        s.y[i] = fmaf(vy, dt, s.y[i]);
+        s.z[i] = fmaf(vz, dt, s.z[i]);
+    }
 }
 
 void launch_kick(bh_ctx *c, float h, uint32_t n, hipStream_t st) {

@@ -246,6 +246,11 @@ __global__ __launch_bounds__(256) void k_gather(const uint32_t *__restrict__ idx
     b.vy[i] = a.vy[s];
     b.vz[i] = a.vz[s];
     b.cid[i] = a.cid[s];
+    if (a.x64) {
+        b.x64[i] = a.x64[s];
+        b.y64[i] = a.y64[s];
+        b.z64[i] = a.z64[s];
+    }
 }
 
 void launch_gather(bh_ctx *c, uint32_t n, hipStream_t st) {

@@ -3,41 +3,15 @@
 // the fly; Sec. I.A: opening angle theta; Sec. VI.A Eq. (1)-(2); Table II
 // "Compute gravity").
 //
-// One 64-lane wavefront walks the tree for one target group:
-//   * a stack of sibling ranges (first << 3 | count - 1); each pass pops up
-//     to 64 cells, one per lane.  Children of opened cells are pushed with
-//     shallower ranges below deeper ones, so the stack holds at most 64
-//     ranges per level (1408).  Its top 256 entries live in an LDS ring; the
-//     rest spill to a per-wave area in device memory in blocks of 64 (any
-//     ring of at least 128 entries works: a spill happens only when more
-//     than ring - 64 entries are resident, a refill only when fewer than 64);
-//   * each lane applies the opening test: distance d from the cell's centre
-//     of mass to the group's box, accept the cell whole iff
-//     d^2 >= (l / theta + delta)^2 (FP32, no contraction);
-//   * accepted cells and the particles of opened leaves are compacted
-//     (ballot + mbcnt) into two LDS index lists; no source data is read
-//     during the traversal;
-//   * a full list is evaluated in chunks of 64 sources: each lane loads one
-//     source record into LDS (the next chunk's loads are issued before the
-//     current chunk is evaluated), then lane = (target, slice) evaluates the
-//     chunk, slice s taking entries s, s + r, ...  A group of g targets uses
-//     one phase with r = floor(64 / g) slices, or two phases (most targets
-//     with ceil(64 / g) slices, the remaining few with many), whichever
-//     needs fewer rounds; the slices are summed at the end.
-// Groups are taken from eight contiguous ranges (one per XCD, blockIdx % 8)
-// through atomic counters, so neighbouring groups share an L2; every wave
-// leaves once all ranges are exhausted.
-#include "bh_internal.h"
-#include "wave.h"
+// The traversal (range stack, opening test, index lists, group scheduling)
+// is in walk_common.h.  This file evaluates the lists: a full list is
+// evaluated in chunks of 64 sources; each lane loads one source record into
+// LDS (the next chunk's loads are issued before the current chunk is
+// evaluated), then lane = (target, slice) evaluates the chunk, slice s
+// taking entries s, s + r, ...; the slices are summed at the end.
+#include "walk_common.h"
 
 namespace bh {
-
-constexpr int kRing = 256;        // LDS window of the range stack (a.ring <= kRing)
-constexpr int kPcCap = 256;       // particle-cell index list
-constexpr int kPcFlush = kPcCap - 64;
-constexpr int kPpCap = 512;       // particle-particle index list
-constexpr int kChunk = 64;        // sources staged per evaluation round
-constexpr int kNull = kChunk;     // staging slot of the null source
 
 struct WalkArgs {
     const float4 *xyzm;                  // sorted positions + mass
@@ -99,12 +73,42 @@ __device__ __forceinline__ void pp_term(const float4 &T, const float4 &P, float 
     acc.z = fmaf(mr3, dz, acc.z);
 }
 
+// ---- FP16 far field --------------------------------------------------------
+//
+// Particle-cell terms in packed FP16 with FP32 accumulation.  Each (group,
+// cell) pair is rescaled by a power of two s so that every quantity in FP16
+// is of order one: with L = |com - gc|_inf + |gh|_inf (gc, gh: group box)
+// and s = 2^-e, 2^(e-1) <= L < 2^e,
+//   d^ = (com - x_i) s = (com - gc) s - rho (x_i - gc) s_g,  rho = s / s_g,
+//   Q^ = Q s^2 / M,  eps^2 -> eps^2 s^2,
+//   a   = (M s^2) [d^ (r^-3 - 3/2 tr Q^ r^-5 + 15/2 d^Q^d^ r^-7) - 3 Q^ d^ r^-5]
+//   phi = (M s)   [-r^-1 + 1/2 tr Q^ r^-3 - 3/2 d^Q^d^ r^-5]      (r = |d^|)
+// where s_g = 2^-e_g scales the group (|x_i - gc| s_g < 1).  Both factors
+// M s^2 and M s stay in FP32.  |d^| <= 2 sqrt(3); a pair whose box distance d
+// has d s < 1/4 (a cell close to a wide group) would push r^-5 out of FP16
+// range, so it is evaluated in FP32 instead.  Particle-particle terms are
+// always FP32.
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ h2 hfma(h2 a, h2 b, h2 c) { return __builtin_elementwise_fma(a, b, c); }
+__device__ __forceinline__ h2 hsplat(float v) {
+    const _Float16 h = (_Float16)v;
+    return h2{h, h};
+}
+
+// staged FP16 record of cell k (a pair (2p, 2p+1) is read as one h2)
+enum { kDx, kDy, kDz, kRho, kE2, kBxx, kByy, kBzz, kBxy, kBxz, kByz, kHtr, kCtr, kH };
+constexpr int kNullPair = kChunk / 2;
+
+struct Far16Lds {
+    _Float16 h[kH][kChunk + 2];
+    float fa[kChunk + 2];    // M s^2
+    float fphi[kChunk + 2];  // M s
+};
+
 struct WalkLds {
     float4 stage[3][kChunk + 1];  // source records of one chunk + the null source
-    uint32_t ring[kRing];
-    uint32_t pcidx[kPcCap];
-    uint32_t ppidx[kPpCap];
-    uint32_t offs[64], firsts[64], starts[64];
+    TravLds T;
 };
 
 // Target roles of a lane in one evaluation phase: T targets, r slices;
@@ -114,7 +118,84 @@ struct Phase {
     bool act;
     float4 tgt;
     float4 acc;
+    h2 ti[3];  // FP16 far field: (x_i - gc) s_g, both halves equal
 };
+
+__device__ __forceinline__ h2 hpair(const Far16Lds &S, int f, uint32_t p) {
+    return reinterpret_cast<const h2 *>(S.h[f])[p];
+}
+
+// One pair of particle-cell terms in FP16 (cells 2p and 2p+1 of the chunk).
+__device__ __forceinline__ void pc16_pair(const h2 ti[3], const Far16Lds &S, uint32_t p,
+                                          float4 &acc) {
+    const h2 rho = hpair(S, kRho, p);
+    const h2 dx = hfma(-rho, ti[0], hpair(S, kDx, p));
+    const h2 dy = hfma(-rho, ti[1], hpair(S, kDy, p));
+    const h2 dz = hfma(-rho, ti[2], hpair(S, kDz, p));
+    const h2 r2 = hfma(dx, dx, hfma(dy, dy, hfma(dz, dz, hpair(S, kE2, p))));
+    h2 ri;
+    ri.x = __builtin_amdgcn_rsqh(r2.x);
+    ri.y = __builtin_amdgcn_rsqh(r2.y);
+    const h2 ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
+    const h2 bxx = hpair(S, kBxx, p), byy = hpair(S, kByy, p), bzz = hpair(S, kBzz, p);
+    const h2 bxy = hpair(S, kBxy, p), bxz = hpair(S, kBxz, p), byz = hpair(S, kByz, p);
+    const h2 qx = hfma(bxx, dx, hfma(bxy, dy, bxz * dz));
+    const h2 qy = hfma(bxy, dx, hfma(byy, dy, byz * dz));
+    const h2 qz = hfma(bxz, dx, hfma(byz, dy, bzz * dz));
+    const h2 dq = hfma(dx, qx, hfma(dy, qy, dz * qz));
+    const h2 a5 = dq * ri5;
+    h2 ph = hfma(hpair(S, kHtr, p), ri3, -ri);
+    ph = hfma(hsplat(0.5f), a5, ph);
+    const h2 u = hfma(hsplat(-2.5f), a5, ri);
+    const h2 s = hfma(hpair(S, kCtr, p), ri5, u * ri2);
+    const h2 ax = hfma(s, dx, qx * ri5), ay = hfma(s, dy, qy * ri5), az = hfma(s, dz, qz * ri5);
+    const float2 fa = reinterpret_cast<const float2 *>(S.fa)[p];
+    const float2 fp = reinterpret_cast<const float2 *>(S.fphi)[p];
+    acc.x = fmaf((float)ax.x, fa.x, acc.x);
+    acc.x = fmaf((float)ax.y, fa.y, acc.x);
+    acc.y = fmaf((float)ay.x, fa.x, acc.y);
+    acc.y = fmaf((float)ay.y, fa.y, acc.y);
+    acc.z = fmaf((float)az.x, fa.x, acc.z);
+    acc.z = fmaf((float)az.y, fa.y, acc.z);
+    acc.w = fmaf((float)ph.x, fp.x, acc.w);
+    acc.w = fmaf((float)ph.y, fp.y, acc.w);
+}
+
+// Evaluate n staged pairs for one phase (null pair past the end).
+__device__ __forceinline__ void eval16_chunk(Phase &ph, uint32_t n, const Far16Lds &S) {
+    const uint32_t r = ph.r;
+    const uint32_t full = n / r, rem = n - full * r;
+    uint32_t k = ph.slice;
+    for (uint32_t j = 0; j < full; ++j, k += r) pc16_pair(ph.ti, S, k, ph.acc);
+    if (rem) pc16_pair(ph.ti, S, ph.slice < rem ? k : (uint32_t)kNullPair, ph.acc);
+}
+
+// Write the FP16 record of one cell (or a null record) into slot k.
+__device__ __forceinline__ void stage16(Far16Lds &S, uint32_t k, bool valid, const float4 &A,
+                                        const float4 &B, const float4 &C, float gcx, float gcy,
+                                        float gcz, float ghmax, int eg, float eps2) {
+    float v[kH], fa = 0.f, fp = 0.f;
+    for (int f = 0; f < kH; ++f) v[f] = 0.f;
+    v[kDx] = 1.f;
+    if (valid) {
+        const float cx = A.x - gcx, cy = A.y - gcy, cz = A.z - gcz;
+        const float L = fmaxf(fmaxf(fabsf(cx), fabsf(cy)), fabsf(cz)) + ghmax;
+        const int e = __builtin_amdgcn_frexp_expf(L);
+        const float s = ldexpf(1.f, -e);
+        const float k2 = s * s / A.w;
+        v[kDx] = cx * s; v[kDy] = cy * s; v[kDz] = cz * s;
+        v[kRho] = ldexpf(1.f, min(eg - e, 14));
+        v[kE2] = fminf(eps2 * s * s, 6.0e4f);
+        v[kBxx] = B.x * k2; v[kByy] = B.y * k2; v[kBzz] = B.z * k2;
+        v[kBxy] = B.w * k2; v[kBxz] = C.x * k2; v[kByz] = C.y * k2;
+        v[kHtr] = C.z * k2; v[kCtr] = C.w * k2;
+        fa = A.w * s * s;
+        fp = A.w * s;
+    }
+    for (int f = 0; f < kH; ++f) S.h[f][k] = (_Float16)v[f];
+    S.fa[k] = fa;
+    S.fphi[k] = fp;
+}
 
 // Evaluate n (<= 64) staged sources for one phase; entries past n read the
 // null source (far away, zero mass) so every round is uniform.
@@ -134,9 +215,9 @@ __device__ __forceinline__ void eval_chunk(Phase &ph, uint32_t n, const WalkLds 
     }
 }
 
-template <bool kEps0>
+template <bool kEps0, bool kF16>
 __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds &L,
-                           uint32_t *spill) {
+                           Far16Lds &S, uint32_t *spill) {
     const uint32_t gb = a.gbeg[g];
     const uint32_t gn = a.gbeg[g + 1] - gb;  // 1..64 by construction
     if (gn == 0u || gn > 64u) {
@@ -147,62 +228,54 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
     // ---- group box
     const bool own = lane < gn;
     const float4 me = a.xyzm[gb + (own ? lane : 0u)];
-    float gcx, gcy, gcz, ghx, ghy, ghz;
-    {
-        float mn = wave_min(own ? me.x : INFINITY), mx = wave_max(own ? me.x : -INFINITY);
-        gcx = (mn + mx) * 0.5f; ghx = (mx - mn) * 0.5f;
-        mn = wave_min(own ? me.y : INFINITY); mx = wave_max(own ? me.y : -INFINITY);
-        gcy = (mn + mx) * 0.5f; ghy = (mx - mn) * 0.5f;
-        mn = wave_min(own ? me.z : INFINITY); mx = wave_max(own ? me.z : -INFINITY);
-        gcz = (mn + mx) * 0.5f; ghz = (mx - mn) * 0.5f;
-    }
+    const GroupBox b = group_box(me, own);
     if (lane == 0) {
-        a.gbox[2 * (size_t)g] = make_float4(gcx, gcy, gcz, 0.f);
-        a.gbox[2 * (size_t)g + 1] = make_float4(ghx, ghy, ghz, 0.f);
+        a.gbox[2 * (size_t)g] = make_float4(b.cx, b.cy, b.cz, 0.f);
+        a.gbox[2 * (size_t)g + 1] = make_float4(b.hx, b.hy, b.hz, 0.f);
     }
 
     // ---- lane roles: one or two phases, whichever needs fewer rounds
     Phase p1, p2;
-    {
-        const uint32_t rs = 64u / gn;
-        const uint32_t cost1 = (64u + rs - 1u) / rs;
-        const uint32_t ra = (64u + gn - 1u) / gn, Ta = 64u / ra, Tb = gn - Ta;
-        const uint32_t rb = Tb ? 64u / Tb : 0u;
-        const uint32_t cost2 = (64u + ra - 1u) / ra + (Tb ? (64u + rb - 1u) / rb : 0u);
-        if (Tb && cost2 < cost1) {
-            p1.T = Ta; p1.r = ra; p2.T = Tb; p2.r = rb;
-        } else {
-            p1.T = gn; p1.r = rs; p2.T = 0; p2.r = 0;
-        }
-        p1.act = lane < p1.T * p1.r;
-        p1.slice = p1.act ? lane / p1.T : 0u;
-        p1.tgt = a.xyzm[gb + (p1.act ? lane % p1.T : 0u)];
-        p1.acc = make_float4(0.f, 0.f, 0.f, 0.f);
-        p2.act = p2.T && lane < p2.T * p2.r;
-        p2.slice = p2.act ? lane / p2.T : 0u;
-        p2.tgt = a.xyzm[gb + (p2.act ? p1.T + lane % p2.T : 0u)];
-        p2.acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    plan_phases(gn, p1.T, p1.r, p2.T, p2.r);
+    p1.act = lane < p1.T * p1.r;
+    p1.slice = p1.act ? lane / p1.T : 0u;
+    p1.tgt = a.xyzm[gb + (p1.act ? lane % p1.T : 0u)];
+    p1.acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    p2.act = p2.T && lane < p2.T * p2.r;
+    p2.slice = p2.act ? lane / p2.T : 0u;
+    p2.tgt = a.xyzm[gb + (p2.act ? p1.T + lane % p2.T : 0u)];
+    p2.acc = make_float4(0.f, 0.f, 0.f, 0.f);
     const bool two = p2.T != 0u;
 
-    uint32_t cnt_pc = 0, cnt_pp = 0, pc_n = 0, pp_n = 0;
-    uint32_t sp = 1, lo = 0;  // stack positions [lo, sp) are in the LDS ring
-    const uint32_t rmask = a.ring - 1u;
+    // FP16 far field: group scale s_g = 2^-eg with |x_i - gc| s_g < 1
+    const float ghmax = fmaxf(fmaxf(b.hx, b.hy), b.hz);
+    const int eg = ghmax > 0.f ? max(__builtin_amdgcn_frexp_expf(ghmax), -100) : -100;
+    if (kF16) {
+        const float sg = ldexpf(1.f, -eg);
+        p1.ti[0] = hsplat((p1.tgt.x - b.cx) * sg);
+        p1.ti[1] = hsplat((p1.tgt.y - b.cy) * sg);
+        p1.ti[2] = hsplat((p1.tgt.z - b.cz) * sg);
+        p2.ti[0] = hsplat((p2.tgt.x - b.cx) * sg);
+        p2.ti[1] = hsplat((p2.tgt.y - b.cy) * sg);
+        p2.ti[2] = hsplat((p2.tgt.z - b.cz) * sg);
+    }
+
     if (lane == 0) {
-        L.ring[0] = 0u;  // the root: first cell 0, one cell
         L.stage[0][kNull] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
         L.stage[1][kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
         L.stage[2][kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    __syncthreads();
+    if (kF16 && lane < 2) {
+        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+        stage16(S, kChunk + lane, false, z4, z4, z4, 0.f, 0.f, 0.f, 0.f, 0, 0.f);
+    }
 
     // evaluate the particle-cell list: stage 64 records at a time, loading
     // the next chunk while the current one is evaluated
-    auto flush_pc = [&](uint32_t n) {
-        if (n == 0) return;
+    auto flush_pc32 = [&](uint32_t n) {
         float4 r0, r1, r2;
         {
-            const uint32_t c = L.pcidx[lane < n ? lane : 0u];
+            const uint32_t c = L.T.pcidx[lane < n ? lane : 0u];
             r0 = a.P0[c]; r1 = a.P1[c]; r2 = a.P2[c];
         }
         for (uint32_t base = 0; base < n; base += kChunk) {
@@ -212,7 +285,7 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
             __syncthreads();
             if (base + kChunk < n) {
                 const uint32_t q = base + kChunk + lane;
-                const uint32_t c = L.pcidx[q < n ? q : base + kChunk];
+                const uint32_t c = L.T.pcidx[q < n ? q : base + kChunk];
                 r0 = a.P0[c]; r1 = a.P1[c]; r2 = a.P2[c];
             }
             eval_chunk<true, kEps0>(p1, m, L, a.eps2);
@@ -220,9 +293,57 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
         }
         __syncthreads();
     };
+    // FP16 far field: each chunk is staged as FP16 pair records; cells too
+    // close to the group for FP16 are compacted into the FP32 staging area
+    auto flush_pc16 = [&](uint32_t n) {
+        float4 r0, r1, r2;
+        {
+            const uint32_t c = L.T.pcidx[lane < n ? lane : 0u];
+            r0 = a.P0[c]; r1 = a.P1[c]; r2 = a.P2[c];
+        }
+        for (uint32_t base = 0; base < n; base += kChunk) {
+            const uint32_t m = n - base < (uint32_t)kChunk ? n - base : (uint32_t)kChunk;
+            const bool valid = lane < m;
+            bool near = false;
+            {
+                const float cx = r0.x - b.cx, cy = r0.y - b.cy, cz = r0.z - b.cz;
+                const float bx = fmaxf(fabsf(cx) - b.hx, 0.f), by = fmaxf(fabsf(cy) - b.hy, 0.f),
+                            bz = fmaxf(fabsf(cz) - b.hz, 0.f);
+                const float d = sqrtf(bx * bx + by * by + bz * bz);
+                const float Lc = fmaxf(fmaxf(fabsf(cx), fabsf(cy)), fabsf(cz)) + ghmax;
+                const float sc = ldexpf(1.f, -(__builtin_amdgcn_frexp_expf(Lc)));
+                near = valid && !(d * sc >= 0.25f);
+            }
+            __syncthreads();
+            stage16(S, lane, valid && !near, r0, r1, r2, b.cx, b.cy, b.cz, ghmax, eg, a.eps2);
+            const uint64_t nm = ballot(near);
+            if (near) {
+                const uint32_t slot = count_below(nm);
+                L.stage[0][slot] = r0; L.stage[1][slot] = r1; L.stage[2][slot] = r2;
+            }
+            const uint32_t nn = (uint32_t)__popcll(nm);
+            __syncthreads();
+            if (base + kChunk < n) {
+                const uint32_t q = base + kChunk + lane;
+                const uint32_t c = L.T.pcidx[q < n ? q : base + kChunk];
+                r0 = a.P0[c]; r1 = a.P1[c]; r2 = a.P2[c];
+            }
+            const uint32_t np = (m + 1u) >> 1;
+            eval16_chunk(p1, np, S);
+            if (two) eval16_chunk(p2, np, S);
+            if (nn) {
+                eval_chunk<true, kEps0>(p1, nn, L, a.eps2);
+                if (two) eval_chunk<true, kEps0>(p2, nn, L, a.eps2);
+            }
+        }
+        __syncthreads();
+    };
+    auto flush_pc = [&](uint32_t n) {
+        if (kF16) flush_pc16(n);
+        else flush_pc32(n);
+    };
     auto flush_pp = [&](uint32_t n) {
-        if (n == 0) return;
-        float4 r0 = a.xyzm[L.ppidx[lane < n ? lane : 0u]];
+        float4 r0 = a.xyzm[L.T.ppidx[lane < n ? lane : 0u]];
         for (uint32_t base = 0; base < n; base += kChunk) {
             const uint32_t m = n - base < (uint32_t)kChunk ? n - base : (uint32_t)kChunk;
             __syncthreads();
@@ -230,7 +351,7 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
             __syncthreads();
             if (base + kChunk < n) {
                 const uint32_t q = base + kChunk + lane;
-                r0 = a.xyzm[L.ppidx[q < n ? q : base + kChunk]];
+                r0 = a.xyzm[L.T.ppidx[q < n ? q : base + kChunk]];
             }
             eval_chunk<false, kEps0>(p1, m, L, a.eps2);
             if (two) eval_chunk<false, kEps0>(p2, m, L, a.eps2);
@@ -238,126 +359,12 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
         __syncthreads();
     };
 
-    while (sp > 0) {
-        // ---- refill the ring from the spill area when the top range is not resident
-        const uint32_t avail = sp < 64u ? sp : 64u;
-        if (sp - avail < lo) {
-            lo -= 64u;
-            L.ring[(lo + lane) & rmask] = spill[lo + lane];
-            __syncthreads();
-        }
-        // ---- pop up to 64 cells from the top ranges
-        uint32_t e = 0, ne = 0;
-        if (lane < avail) {
-            e = L.ring[(sp - 1 - lane) & rmask];
-            ne = (e & 7u) + 1u;
-        }
-        const uint32_t incl = wave_incl_scan(ne, lane);
-        const uint32_t excl = incl - ne;
-        const uint32_t nfull = (uint32_t)__popcll(ballot(lane < avail && incl <= 64u));
-        const uint32_t tall = shfl(incl, (int)avail - 1);
-        const uint32_t total = tall < 64u ? tall : 64u;
-        L.starts[lane] = 0u;
-        __syncthreads();
-        if (lane < avail && excl < 64u) L.starts[excl] = 1u;
-        __syncthreads();
-        const uint64_t smask = ballot(L.starts[lane] != 0u);
-        const bool have = lane < total;
-        const uint32_t j = (uint32_t)__popcll(smask & mask_le(lane)) - 1u;
-        const uint32_t ej = shfl(e, (int)j), xj = shfl(excl, (int)j);
-        const uint32_t cell = (ej >> 3) + (lane - xj);
-        const uint32_t sp_new = sp - nfull;
-        if (nfull < avail && lane == nfull && excl < 64u) {
-            const uint32_t taken = 64u - excl;  // the rest of this range stays on top
-            L.ring[(sp_new - 1) & rmask] = (((e >> 3) + taken) << 3) | (ne - taken - 1u);
-        }
-
-        // ---- opening test
-        float4 A = make_float4(0.f, 0.f, 0.f, 0.f);
-        uint2 N = make_uint2(0u, 0u);
-        if (have) {
-            A = a.wA[cell];
-            N = a.wN[cell];
-        }
-        const float dxm = fmaxf(fabsf(A.x - gcx) - ghx, 0.f);
-        const float dym = fmaxf(fabsf(A.y - gcy) - ghy, 0.f);
-        const float dzm = fmaxf(fabsf(A.z - gcz) - ghz, 0.f);
-        float d2 = dxm * dxm + dym * dym;
-        d2 = d2 + dzm * dzm;
-        const bool accept = have && d2 >= A.w;
-        const bool isleaf = (N.y & kLeafBit) != 0u;
-        const bool openleaf = have && !accept && isleaf;
-        const bool openint = have && !accept && !isleaf;
-
-        // ---- accepted cells -> particle-cell index list
-        const uint64_t am = ballot(accept);
-        if (accept) L.pcidx[pc_n + count_below(am)] = cell;
-        const uint32_t nacc = (uint32_t)__popcll(am);
-        pc_n += nacc;
-        cnt_pc += nacc;
-
-        // ---- opened internal cells -> their children ranges, shallowest lowest
-        const uint64_t om = ballot(openint);
-        const uint32_t npush = (uint32_t)__popcll(om);
-        if (sp_new + npush > (uint32_t)kStackMax) {  // cannot happen: 64 ranges per level
-            if (lane == 0) atomicOr(a.status, kStOverflow);
-            break;
-        }
-        if (sp_new + npush > lo + a.ring) {
-            // spill the 64 lowest resident entries (all below sp_new)
-            __syncthreads();
-            spill[lo + lane] = L.ring[(lo + lane) & rmask];
-            lo += 64u;
-            __syncthreads();
-        }
-        if (openint) {
-            const uint32_t above = lane == 63u ? 0u : (uint32_t)__popcll(om >> (lane + 1u));
-            L.ring[(sp_new + above) & rmask] = (N.x << 3) | (N.y - 1u);
-        }
-        sp = sp_new + npush;
-
-        // ---- particles of opened leaves -> particle-particle index list
-        const uint32_t lc = openleaf ? (N.y & ~kLeafBit) : 0u;
-        const uint32_t lincl = wave_incl_scan(lc, lane);
-        const uint32_t P = shfl(lincl, 63);
-        if (P > 0u) {
-            L.offs[lane] = lincl - lc;
-            L.firsts[lane] = N.x;
-            __syncthreads();
-            cnt_pp += P;
-            for (uint32_t base = 0; base < P;) {
-                if (pp_n == (uint32_t)kPpCap) {
-                    flush_pp(pp_n);
-                    pp_n = 0;
-                }
-                const uint32_t room = (uint32_t)kPpCap - pp_n;
-                const uint32_t take = room < P - base ? room : P - base;
-                for (uint32_t q = lane; q < take; q += 64u) {
-                    const uint32_t f = base + q;
-                    uint32_t s = 0;
-#pragma unroll
-                    for (uint32_t step = 32; step > 0; step >>= 1)
-                        if (L.offs[s + step] <= f) s += step;
-                    L.ppidx[pp_n + q] = L.firsts[s] + (f - L.offs[s]);
-                }
-                pp_n += take;
-                base += take;
-                __syncthreads();
-            }
-        }
-        __syncthreads();
-        if (pc_n > (uint32_t)kPcFlush) {
-            flush_pc(pc_n);
-            pc_n = 0;
-        }
-    }
-    __syncthreads();
-    flush_pc(pc_n);
-    flush_pp(pp_n);
+    uint32_t cnt_pc, cnt_pp;
+    const TreeView tv{a.wA, a.wN, a.ring, a.status};
+    traverse(tv, b, lane, L.T, spill, cnt_pc, cnt_pp, flush_pc, flush_pp);
 
     // ---- sum the slices of each target (staging area reused)
     float4 res = make_float4(0.f, 0.f, 0.f, 0.f);
-    __syncthreads();
     L.stage[0][lane] = p1.acc;
     __syncthreads();
     if (lane < p1.T)
@@ -387,23 +394,23 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
     __syncthreads();
 }
 
-template <bool kEps0>
+template <bool kEps0, bool kF16>
+__device__ __forceinline__ void walk_loop(const WalkArgs &a, WalkLds &L, Far16Lds &S) {
+    const uint32_t lane = threadIdx.x;
+    uint32_t *spill = a.spill + (size_t)blockIdx.x * kStackMax;
+    for_each_group(*a.ngroups, a.work, lane,
+                   [&](uint32_t g) { walk_group<kEps0, kF16>(a, g, lane, L, S, spill); });
+}
+
+template <bool kEps0, bool kF16>
 __global__ __launch_bounds__(64) void k_walk(WalkArgs a) {
     __shared__ WalkLds L;
-    const uint32_t lane = threadIdx.x;
-    const uint32_t ng = *a.ngroups;
-    uint32_t *spill = a.spill + (size_t)blockIdx.x * kStackMax;
-    for (uint32_t k = 0; k < 8; ++k) {
-        const uint32_t part = (blockIdx.x + k) & 7u;
-        const uint32_t r0 = (uint32_t)(((uint64_t)ng * part) >> 3);
-        const uint32_t r1 = (uint32_t)(((uint64_t)ng * (part + 1)) >> 3);
-        for (;;) {
-            uint32_t t = 0;
-            if (lane == 0) t = atomicAdd(&a.work[part], 1u);
-            t = uniform(t);
-            if (t >= r1 - r0) break;
-            walk_group<kEps0>(a, r0 + t, lane, L, spill);
-        }
+    if constexpr (kF16) {
+        __shared__ Far16Lds S;
+        walk_loop<kEps0, true>(a, L, S);
+    } else {
+        // the FP32 walk never touches the FP16 staging area
+        walk_loop<kEps0, false>(a, L, *reinterpret_cast<Far16Lds *>(&L));
     }
 }
 
@@ -413,7 +420,7 @@ __global__ void k_reset_work(uint32_t *work) {
 
 int walk_blocks_per_cu() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<false>, 64, 0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_walk<false, false>, 64, 0) != hipSuccess ||
         nb < 1)
         nb = 4;
     return nb;
@@ -433,10 +440,15 @@ void launch_walk(bh_ctx *c, float eps, hipStream_t st) {
     hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(64), 0, st, c->work);
     (void)hipEventRecord(c->ev[4], st);
     c->ev_rec[4] = true;
-    if (eps == 0.f)
-        hipLaunchKernelGGL(k_walk<true>, dim3(c->walk_grid), dim3(64), 0, st, a);
+    const bool f16 = c->p.far_fp16 != 0;
+    if (eps == 0.f && f16)
+        hipLaunchKernelGGL((k_walk<true, true>), dim3(c->walk_grid), dim3(64), 0, st, a);
+    else if (eps == 0.f)
+        hipLaunchKernelGGL((k_walk<true, false>), dim3(c->walk_grid), dim3(64), 0, st, a);
+    else if (f16)
+        hipLaunchKernelGGL((k_walk<false, true>), dim3(c->walk_grid), dim3(64), 0, st, a);
     else
-        hipLaunchKernelGGL(k_walk<false>, dim3(c->walk_grid), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((k_walk<false, false>), dim3(c->walk_grid), dim3(64), 0, st, a);
     (void)hipEventRecord(c->ev[5], st);
     c->ev_rec[5] = true;
 }

@@ -14,9 +14,9 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device())
 
 
-def gpu_tree(pos, mass, nleaf=16, ncrit=64, vel=None):
+def gpu_tree(pos, mass, nleaf=16, ncrit=64, vel=None, far_fp16=False):
     from paper_1412_0659_amd import Tree
-    t = Tree(max(1, len(mass)), nleaf, ncrit)
+    t = Tree(max(1, len(mass)), nleaf, ncrit, far_fp16)
     if vel is None:
         t.build(to_dev(pos), to_dev(mass))
     else:

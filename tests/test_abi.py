@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "bh.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return re.findall(r"^\s*(?:int|const char \*)\s*(\w+)\s*\(", src, flags=re.M)
+    return re.findall(r"^\s*(?:int|int64_t|const char \*)\s*(\w+)\s*\(", src, flags=re.M)
 
 
 def test_header_declares_the_boundary():
@@ -36,7 +36,7 @@ def test_host_argument_checks():
     out = ctypes.c_void_p()
     assert L.bh_create(ctypes.byref(out), 0, None) == bh.binding.BH_EINVAL
     assert L.bh_create(ctypes.byref(out), -5, None) == bh.binding.BH_EINVAL
-    for nleaf, ncrit, f16 in [(0, 64, 0), (16, 0, 0), (16, 65, 0), (65, 64, 0), (16, 64, 1)]:
+    for nleaf, ncrit, f16 in [(0, 64, 0), (16, 0, 0), (16, 65, 0), (65, 64, 0), (16, 64, 2)]:
         p = bh.binding.bh_params(nleaf, ncrit, f16, 0)
         assert L.bh_create(ctypes.byref(out), 100, ctypes.byref(p)) == bh.binding.BH_EINVAL
     # too many particles for the 29-bit cell index of the walk stack
