@@ -152,7 +152,8 @@ int bh_load_state(bh_ctx *ctx, const void *src, int64_t n, hipStream_t s);
 
 /* Polar grid of the surface-density observable. */
 typedef struct bh_cic_grid {
-    float r_min, r_max;   /* radial range, 0 <= r_min < r_max */
+    float r_min, r_max;   /* radial range, 0 < r_min < r_max; particles outside
+                             it are dropped (the inner cut bounds d(phi)/dx) */
     int32_t n_r, n_phi;   /* cells; n_r * n_phi <= 65536 */
 } bh_cic_grid;
 

@@ -18,6 +18,13 @@ Steps (paper: Bedorf et al., SC14, arXiv:1412.0659):
                                 Eq. (1)-(2); Plummer softening (Sec. IV)
   direct summation              the theta -> 0 limit of Sec. I.A
   leapfrog (KDK)                Sec. III.B.2 (second-order leap-frog)
+  differentiation form          not in the paper: the walk's decisions are
+                                recorded and frozen, the forces replayed in
+                                FP64 and differentiated by a hand-written
+                                reverse sweep (force VJP, KDK transpose)
+  surface density               the face-on surface density the paper shows
+                                for its Milky Way run (Sec. IV), as bilinear
+                                cloud-in-cell on a polar grid
 """
 from __future__ import annotations
 
@@ -411,3 +418,167 @@ def replay_vjp(d: Decisions, x_sorted, m_sorted, eps, u_sorted):
     L.orc_replay_vjp(*_topo(d), x, m, float(eps), M, com, Q, _f64(u_sorted).reshape(-1), lM, lcom,
                      lQ, gx, gm)
     return gx.reshape(n, 3), gm
+
+
+def frozen_force(d: Decisions, x, m, eps):
+    """Frozen-decision accelerations at FP64 caller-order positions x."""
+    perm = d.tree.perm
+    a_s = replay(d, np.asarray(x, np.float64)[perm], np.asarray(m, np.float64)[perm], eps)[0]
+    a = np.empty_like(a_s)
+    a[perm] = a_s
+    return a
+
+
+def frozen_force_vjp(d: Decisions, x, m, eps, u):
+    """u^T d(acc)/d(x, m) of frozen_force (caller order)."""
+    perm = d.tree.perm
+    gx_s, gm_s = replay_vjp(d, np.asarray(x, np.float64)[perm], np.asarray(m, np.float64)[perm],
+                            eps, np.asarray(u, np.float64)[perm])
+    gx = np.empty_like(gx_s)
+    gm = np.empty_like(gm_s)
+    gx[perm] = gx_s
+    gm[perm] = gm_s
+    return gx, gm
+
+
+def trajectory_decisions(positions, mass, theta, nleaf=NLEAF, ncrit=NCRIT):
+    """Decisions of the walk at each stored step (positions: list of FP32
+    [N,3] arrays, caller order): the trees are built from exactly those
+    FP32 positions."""
+    return [record_decisions(build_tree(p, mass, nleaf, ncrit), theta) for p in positions]
+
+
+def leapfrog_frozen(x0, v0, m, dt, decs, eps):
+    """K = len(decs) - 1 kick-drift-kick steps in FP64, the force at step n
+    taken with the frozen decisions decs[n].  Returns (x_K, v_K, [x_n])."""
+    h = 0.5 * dt
+    x = np.asarray(x0, np.float64).copy()
+    v = np.asarray(v0, np.float64).copy()
+    xs = [x.copy()]
+    a = frozen_force(decs[0], x, m, eps)
+    for n in range(len(decs) - 1):
+        v = v + h * a
+        x = x + dt * v
+        xs.append(x.copy())
+        a = frozen_force(decs[n + 1], x, m, eps)
+        v = v + h * a
+    return x, v, xs
+
+
+def leapfrog_frozen_vjp(x0, v0, m, dt, decs, eps, gxK, gvK):
+    """Reverse sweep of leapfrog_frozen: cotangents of (x_K, v_K) ->
+    gradients with respect to (x_0, v_0, m).  The two kicks that meet at an
+    interior position share the cotangent, so each x_n takes one VJP with
+    weight dt (dt/2 at n = 0 and n = K)."""
+    h = 0.5 * dt
+    K = len(decs) - 1
+    _, _, xs = leapfrog_frozen(x0, v0, m, dt, decs, eps)
+    gx = np.asarray(gxK, np.float64).copy()
+    gv = np.asarray(gvK, np.float64).copy()
+    gm = np.zeros(len(m))
+    g1, gm1 = frozen_force_vjp(decs[K], xs[K], m, eps, gv)
+    gx += h * g1
+    gm += h * gm1
+    for j in reversed(range(K)):
+        gv = gv + dt * gx
+        c = dt if j > 0 else h
+        g1, gm1 = frozen_force_vjp(decs[j], xs[j], m, eps, gv)
+        gx += c * g1
+        gm += c * gm1
+    return gx, gv, gm
+
+
+# --- surface density observable (cloud-in-cell on a polar grid) ---------------
+
+def cic_density(pos, mass, sel, grid):
+    """Face-on surface density of the selected particles on the polar grid
+    (r_min, r_max, n_r, n_phi): cell centres R_i = r_min + (i + 1/2) dR,
+    phi_j = (j + 1/2) dphi; bilinear cloud-in-cell weights in (R, phi),
+    phi periodic, cells outside [0, n_r) dropped; particles with R outside
+    [r_min, r_max) dropped (the inner cut keeps d(phi)/dx ~ 1/R bounded);
+    mass / cell area.  FP64."""
+    r0, r1, nr, nphi = grid
+    pos = np.asarray(pos, np.float64)
+    m = np.asarray(mass, np.float64)
+    if sel is not None:
+        pos, m = pos[sel], m[sel]
+    R = np.hypot(pos[:, 0], pos[:, 1])
+    keep = (R >= r0) & (R < r1)
+    pos, m = pos[keep], m[keep]
+    dr = (r1 - r0) / nr
+    dphi = 2 * np.pi / nphi
+    R = np.hypot(pos[:, 0], pos[:, 1])
+    phi = np.mod(np.arctan2(pos[:, 1], pos[:, 0]), 2 * np.pi)
+    u = (R - r0) / dr - 0.5
+    v = phi / dphi - 0.5
+    i0 = np.floor(u).astype(np.int64)
+    j0 = np.floor(v).astype(np.int64)
+    fu, fv = u - i0, v - j0
+    acc = np.zeros((nr, nphi))
+    for a in (0, 1):
+        for b in (0, 1):
+            w = (fu if a else 1 - fu) * (fv if b else 1 - fv) * m
+            i = i0 + a
+            j = np.mod(j0 + b, nphi)
+            ok = (i >= 0) & (i < nr)
+            np.add.at(acc, (i[ok], j[ok]), w[ok])
+    redge = r0 + dr * np.arange(nr + 1)
+    area = 0.5 * dphi * (redge[1:] ** 2 - redge[:-1] ** 2)
+    return acc / area[:, None]
+
+
+def cic_density_vjp(pos, mass, sel, grid, g):
+    """Gradient of sum(g * cic_density) with respect to pos and mass."""
+    r0, r1, nr, nphi = grid
+    pos = np.asarray(pos, np.float64)
+    m_all = np.asarray(mass, np.float64)
+    idx = np.arange(len(m_all)) if sel is None else np.nonzero(sel)[0]
+    Rall = np.hypot(pos[idx, 0], pos[idx, 1])
+    idx = idx[(Rall >= r0) & (Rall < r1)]
+    p, m = pos[idx], m_all[idx]
+    dr = (r1 - r0) / nr
+    dphi = 2 * np.pi / nphi
+    x, y = p[:, 0], p[:, 1]
+    R = np.hypot(x, y)
+    phi = np.mod(np.arctan2(y, x), 2 * np.pi)
+    u = (R - r0) / dr - 0.5
+    v = phi / dphi - 0.5
+    i0 = np.floor(u).astype(np.int64)
+    j0 = np.floor(v).astype(np.int64)
+    fu, fv = u - i0, v - j0
+    redge = r0 + dr * np.arange(nr + 1)
+    area = 0.5 * dphi * (redge[1:] ** 2 - redge[:-1] ** 2)
+    dfu = np.zeros(len(m))
+    dfv = np.zeros(len(m))
+    dm = np.zeros(len(m))
+    for a in (0, 1):
+        for b in (0, 1):
+            i = i0 + a
+            j = np.mod(j0 + b, nphi)
+            ok = (i >= 0) & (i < nr)
+            gb = np.zeros(len(m))
+            gb[ok] = g[i[ok], j[ok]] / area[i[ok]]
+            wu = fu if a else 1 - fu
+            wv = fv if b else 1 - fv
+            dm += gb * wu * wv
+            dfu += gb * m * (1 if a else -1) * wv
+            dfv += gb * m * wu * (1 if b else -1)
+    du, dv = dfu / dr, dfv / dphi
+    gpos = np.zeros_like(pos)
+    gpos[idx, 0] = du * x / R - dv * y / R ** 2
+    gpos[idx, 1] = du * y / R + dv * x / R ** 2
+    gmass = np.zeros_like(m_all)
+    gmass[idx] = dm
+    return gpos, gmass
+
+
+def kdk_positions(pos, vel, mass, dt, steps, force):
+    """FP32 roundings of the positions at steps 0..K of leapfrog(): the
+    inputs of the trees a tree-code run builds along its trajectory."""
+    m = _f64(mass)
+    x, v = _f64(pos).reshape(-1, 3), _f64(vel).reshape(-1, 3)
+    out = [x.astype(np.float32)]
+    for _ in range(steps):
+        x, v = leapfrog(x, v, m, dt, 1, force)
+        out.append(x.astype(np.float32))
+    return out

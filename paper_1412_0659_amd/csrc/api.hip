@@ -471,7 +471,7 @@ int bh_load_state(bh_ctx *c, const void *src, int64_t n64, hipStream_t s) {
 }
 
 static int check_grid(bh_ctx *c, const bh_cic_grid *g) {
-    if (!g || !(g->r_min >= 0.f) || !(g->r_max > g->r_min) || !std::isfinite(g->r_max) ||
+    if (!g || !(g->r_min > 0.f) || !(g->r_max > g->r_min) || !std::isfinite(g->r_max) ||
         g->n_r < 1 || g->n_phi < 1 || (int64_t)g->n_r * g->n_phi > 65536)
         return fail(c, BH_EINVAL, "bad surface-density grid");
     return BH_OK;

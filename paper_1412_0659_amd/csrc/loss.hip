@@ -5,13 +5,15 @@
 // Cell centres R_i = r_min + (i + 1/2) dR, phi_j = (j + 1/2) dphi; a particle
 // at (R, phi) with u = (R - r_min)/dR - 1/2 and v = phi/dphi - 1/2 spreads its
 // mass bilinearly over the four cells around (u, v) (phi periodic, cells
-// outside [0, n_r) dropped); density = mass / (dphi (R_{i+1}^2 - R_i^2) / 2).
+// outside [0, n_r) dropped); particles with R outside [r_min, r_max) are
+// dropped, so d(phi)/dx ~ 1/R stays bounded; density = mass /
+// (dphi (R_{i+1}^2 - R_i^2) / 2).
 #include "bh_internal.h"
 
 namespace bh {
 
 struct CicGeom {
-    float rmin, dr, dphi;
+    float rmin, rmax, dr, dphi;
     int nr, nphi;
 };
 
@@ -43,6 +45,7 @@ __global__ __launch_bounds__(256) void k_cic_deposit(const float *__restrict__ p
     float R, fu, fv;
     int i0, j0;
     cic_coords(pos[3 * (size_t)k], pos[3 * (size_t)k + 1], g, R, i0, j0, fu, fv);
+    if (!(R >= g.rmin && R < g.rmax)) return;
     const float m = mass[k];
     for (int a = 0; a < 2; ++a) {
         const int i = i0 + a;
@@ -75,6 +78,7 @@ __global__ __launch_bounds__(256) void k_cic_vjp(const float *__restrict__ pos,
     float R, fu, fv;
     int i0, j0;
     cic_coords(x, y, g, R, i0, j0, fu, fv);
+    if (!(R >= g.rmin && R < g.rmax)) return;
     const float m = mass[k];
     float dfu = 0.f, dfv = 0.f, dm = 0.f;  // dL/dfu, dL/dfv, dL/dm
     for (int a = 0; a < 2; ++a) {
@@ -94,7 +98,7 @@ __global__ __launch_bounds__(256) void k_cic_vjp(const float *__restrict__ pos,
     }
     // u = (R - rmin)/dR - 1/2, v = phi/dphi - 1/2; dR/dx = x/R, dphi/dx = -y/R^2
     const float du = dfu / g.dr, dv = dfv / g.dphi;
-    const float iR = R > 0.f ? 1.f / R : 0.f;
+    const float iR = 1.f / R;
     if (g_pos) {
         g_pos[3 * (size_t)k] += du * x * iR - dv * y * iR * iR;
         g_pos[3 * (size_t)k + 1] += du * y * iR + dv * x * iR * iR;
@@ -104,7 +108,7 @@ __global__ __launch_bounds__(256) void k_cic_vjp(const float *__restrict__ pos,
 
 void launch_cic(const float *pos, const float *mass, const uint8_t *sel, uint32_t n, float rmin,
                 float rmax, int nr, int nphi, double *scratch, float *density, hipStream_t st) {
-    const CicGeom g{rmin, (rmax - rmin) / nr, 6.28318530717958647692f / nphi, nr, nphi};
+    const CicGeom g{rmin, rmax, (rmax - rmin) / nr, 6.28318530717958647692f / nphi, nr, nphi};
     const uint32_t nb = (uint32_t)nr * (uint32_t)nphi;
     launch_fill_u32(reinterpret_cast<uint32_t *>(scratch), 0u, 2ull * nb, st);
     if (n) hipLaunchKernelGGL(k_cic_deposit, dim3(cdiv(n, 256)), dim3(256), 0, st, pos, mass, sel, n, g, scratch);
@@ -115,7 +119,7 @@ void launch_cic(const float *pos, const float *mass, const uint8_t *sel, uint32_
 void launch_cic_vjp(const float *pos, const float *mass, const uint8_t *sel, uint32_t n,
                     float rmin, float rmax, int nr, int nphi, const float *gden, float *g_pos,
                     float *g_mass, hipStream_t st) {
-    const CicGeom g{rmin, (rmax - rmin) / nr, 6.28318530717958647692f / nphi, nr, nphi};
+    const CicGeom g{rmin, rmax, (rmax - rmin) / nr, 6.28318530717958647692f / nphi, nr, nphi};
     if (n) hipLaunchKernelGGL(k_cic_vjp, dim3(cdiv(n, 256)), dim3(256), 0, st, pos, mass, sel, n, g, gden, g_pos, g_mass);
 }
 

@@ -206,3 +206,25 @@ def disk_halo_scaled(n: int, seed: int, disk_fraction: float = 0.2) -> Snapshot:
     """The disk + halo model at an arbitrary particle count (1:4 disk:halo)."""
     nd = int(round(n * disk_fraction))
     return disk_halo(nd, n - nd, seed)
+
+
+def perturbed(s: Snapshot, seed: int, rel: float = 0.05) -> Snapshot:
+    """The same particles with every position and velocity component scaled
+    by a seeded factor 1 + rel * N(0, 1): initial conditions for a target
+    snapshot."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fp = 1.0 + rel * rng.standard_normal(s.pos.shape)
+    fv = 1.0 + rel * rng.standard_normal(s.vel.shape)
+    return Snapshot((s.pos * fp).astype(np.float32), (s.vel * fv).astype(np.float32),
+                    s.mass.copy(), s.is_disk.copy())
+
+
+# The differentiation workload: disk + halo, 64 KDK steps, the squared error
+# of the disk's face-on (R, phi) surface density against the density reached
+# from perturbed initial conditions.
+DIFF_WORKLOADS = {
+    "disk_halo_1m_adjoint": dict(n=1_000_000, seed=5, target_seed=6, eps=0.005, theta=0.4,
+                                 dt=1e-3, steps=64, every=8, grid=(0.2, 4.0, 16, 32)),
+    "disk_halo_4096_adjoint": dict(n=4096, seed=7, target_seed=8, eps=0.005, theta=0.4,
+                                   dt=1e-3, steps=64, every=8, grid=(0.2, 4.0, 8, 8)),
+}
