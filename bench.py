@@ -81,6 +81,114 @@ def cpu_baseline(snap, theta, eps, budget_s=12.0):
     }
 
 
+def _rel(a, ref):
+    import numpy as np
+    if a.ndim == 1:
+        return np.abs(a - ref) / np.abs(ref)
+    return np.sqrt(((a - ref) ** 2).sum(1) / (ref ** 2).sum(1))
+
+
+def _timed_force(tree, theta, eps, reps):
+    """Force `reps` times after one warm-up; mean walk-kernel ms and the last
+    accelerations / potentials (caller order, float64 numpy)."""
+    tree.force(theta, eps)
+    tree.sync()
+    ms = []
+    for _ in range(reps):
+        acc, pot = tree.force(theta, eps)
+        ms.append(tree.stats()["ms_walk"])
+    st = tree.stats()
+    return (sum(ms) / len(ms), acc.double().cpu().numpy(), pot.double().cpu().numpy(), st)
+
+
+def precision(snap, theta, eps, nsample=65536, seed=40, reps=3, log=print):
+    """Plain FP32 walk vs the FP16 far-field walk on the same particles: walk
+    time and force error against the GPU's FP64 direct sum at a seeded
+    uniform subsample of targets."""
+    import numpy as np
+    import torch
+
+    import paper_1412_0659_amd as bh
+    from workloads import ics
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(snap.pos).to(dev)
+    mass = torch.from_numpy(snap.mass).to(dev)
+    idx = ics.subsample(snap.n, nsample, seed)
+    tg = torch.from_numpy(idx.astype(np.int64)).to(dev)
+    out = {"theta": theta, "eps": eps,
+           "sample": f"{len(idx)} targets, seeded uniform subsample (seed {seed}) of "
+                     f"{snap.n}; reference: FP64 direct sum on the GPU (tree_direct)"}
+    ref = None
+    for name, f16 in (("fp32", False), ("fp16_far", True)):
+        tree = bh.Tree(snap.n, far_fp16=f16)
+        tree.build(pos, mass)
+        if ref is None:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ra, rp = tree.direct(tg, eps)
+            tree.sync()
+            out["direct_s"] = time.perf_counter() - t0
+            ref = (ra.cpu().numpy(), rp.cpu().numpy())
+        ms, acc, pot, st = _timed_force(tree, theta, eps, reps)
+        tree.close()
+        ea = _rel(acc[idx], ref[0])
+        ep = _rel(pot[idx], ref[1])
+        out[name] = {"walk_ms": ms, "err_acc_median": float(np.median(ea)),
+                     "err_acc_p99": float(np.percentile(ea, 99)),
+                     "err_pot_median": float(np.median(ep)),
+                     "n_pp": st["n_pp"], "n_pc": st["n_pc"],
+                     "tflops_walk": paper_flops(st["n_pp"], st["n_pc"]) / (ms * 1e-3) / 1e12}
+        log(f"[bench] precision {name}: walk {ms:.2f} ms, acc err median "
+            f"{out[name]['err_acc_median']:.2e} p99 {out[name]['err_acc_p99']:.2e}")
+    out["speedup_walk_fp16_far"] = out["fp32"]["walk_ms"] / out["fp16_far"]["walk_ms"]
+    return out
+
+
+def adjoint(name="disk_halo_1m_adjoint", log=print):
+    """The differentiation workload: K KDK steps forward with checkpoints,
+    surface-density loss, reverse sweep; forward and backward wall time."""
+    import numpy as np
+    import torch
+
+    import paper_1412_0659_amd as bh
+    from paper_1412_0659_amd.autograd import leapfrog, surface_density
+    from workloads import ics
+    w = ics.DIFF_WORKLOADS[name]
+    s = ics.disk_halo_scaled(w["n"], w["seed"])
+    tgt_ic = ics.perturbed(s, w["target_seed"])
+    dev = torch.device("cuda:0")
+    sel = torch.from_numpy(s.is_disk.astype(np.uint8)).to(dev)
+    tree = bh.Tree(s.n, adjoint=True, pos_fp64=True)
+    # target: the density the perturbed initial conditions reach after K steps
+    with torch.no_grad():
+        xt, _ = leapfrog(torch.from_numpy(tgt_ic.pos).to(dev), torch.from_numpy(tgt_ic.vel).to(dev),
+                         torch.from_numpy(s.mass).to(dev), tree, w["dt"], w["steps"], w["theta"],
+                         w["eps"], w["every"])
+        target = surface_density(xt, torch.from_numpy(s.mass).to(dev), sel, tree, w["grid"])
+    x0 = torch.from_numpy(s.pos).to(dev).requires_grad_(True)
+    v0 = torch.from_numpy(s.vel).to(dev).requires_grad_(True)
+    m = torch.from_numpy(s.mass).to(dev).requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xK, _ = leapfrog(x0, v0, m, tree, w["dt"], w["steps"], w["theta"], w["eps"], w["every"])
+    loss = ((surface_density(xK, m, sel, tree, w["grid"]) - target) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    tree.close()
+    fwd, bwd = t1 - t0, t2 - t1
+    log(f"[bench] adjoint: forward {fwd:.2f} s, backward {bwd:.2f} s")
+    finite = all(bool(torch.isfinite(a.grad).all()) for a in (x0, v0, m))
+    return {"workload": name, "n": s.n, "steps": w["steps"], "checkpoint_every": w["every"],
+            "theta": w["theta"], "eps": w["eps"], "dt": w["dt"], "grid": list(w["grid"]),
+            "loss": float(loss), "forward_s": fwd, "backward_s": bwd,
+            "backward_over_forward": bwd / fwd,
+            "ms_per_step_forward": 1e3 * fwd / w["steps"],
+            "ms_per_step_backward": 1e3 * bwd / w["steps"], "grad_finite": finite}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,6 +196,11 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="disk_halo_13m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy five times (the "
+                         "reference kernel for scaling the HBM byte counters)")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args(argv)
 
@@ -101,6 +214,16 @@ def main(argv=None):
 
     import paper_1412_0659_amd as bh
     from workloads import ics
+
+    if args.copy_calibration:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4,
+                          "launches": 5}))
+        return 0
 
     w = ics.WORKLOADS[args.workload]
     theta, eps, dt = w["theta"], w["eps"], w.get("dt", 1e-3)
@@ -172,6 +295,11 @@ def main(argv=None):
                      "flops_convention": "23 per p-p, 65 per p-c (paper Sec. VI.A)"},
     }
     tree.close()
+    del pos, vel, mass
+    if not args.no_precision:
+        out["precision"] = precision(snap, theta, eps, log=log)
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint(log=log)
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(snap, theta, eps)

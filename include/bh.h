@@ -112,6 +112,21 @@ int bh_set_state(bh_ctx *ctx, const float *pos, const float *vel, const float *m
  * BH_ESTATE (no tree built). */
 int tree_force(bh_ctx *ctx, float theta, float eps, float *acc, float *pot, hipStream_t s);
 
+/* Direct summation in FP64 at chosen particles over all n particles of the
+ * current state: the theta -> 0 limit of the tree force (Sec. I.A), the
+ * reference the error of tree_force is stated against.  Positions are the
+ * FP32 values the tree is built from; the self pair is skipped, and so is a
+ * zero-separation pair when eps = 0.
+ *   targets  device, [nt] caller indices in [0, n)
+ *   acc      device, [nt][3] FP64, overwritten
+ *   pot      device, [nt] FP64, overwritten
+ * Spans of sources are combined with FP64 atomics (last-bit differences
+ * between runs are possible).  Errors: BH_EINVAL (bad eps, nt < 0, null
+ * pointer; an index outside [0, n) leaves its outputs 0 and is latched as
+ * BH_EINVAL for the next synchronising call), BH_ESTATE (no tree). */
+int tree_direct(bh_ctx *ctx, const int64_t *targets, int64_t nt, float eps, double *acc,
+                double *pot, hipStream_t s);
+
 /* One kick-drift-kick step (Sec. III.B.2): v += a dt/2; x += v dt; rebuild
  * the tree; a = force(x); v += a dt/2.  The force at the current state is
  * computed first when the last call did not leave one for (theta, eps).

@@ -63,7 +63,7 @@ SYMBOLS = ["bh_create", "bh_destroy", "tree_build", "bh_set_state", "tree_force"
            "leapfrog_step", "bh_get_state", "bh_sync", "bh_stats_get", "bh_export",
            "bh_strerror", "bh_last_error", "tree_force_vjp", "leapfrog_vjp_drift",
            "bh_state_bytes", "bh_save_state", "bh_load_state", "bh_cic_density",
-           "bh_cic_density_vjp"]
+           "bh_cic_density_vjp", "tree_direct"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -101,6 +101,7 @@ def load():
                            c_int),
         "bh_cic_density_vjp": ([_vp, _vp, _vp, _vp, i64, ctypes.POINTER(bh_cic_grid), _vp, _vp,
                                 _vp, _vp], c_int),
+        "tree_direct": ([_vp, _vp, i64, f32, _vp, _vp, _vp], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -208,6 +209,27 @@ def _u8ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def tree_direct(ctx, targets, eps, acc=None, pot=None, stream=None):
+    """FP64 direct sum at caller indices `targets` (int64 CUDA tensor);
+    returns (acc [nt,3], pot [nt]) as float64 CUDA tensors."""
+    import torch
+    if not (isinstance(targets, torch.Tensor) and targets.is_cuda and targets.is_contiguous()
+            and targets.dtype == torch.int64):
+        raise TypeError("expected a contiguous int64 CUDA tensor of targets")
+    nt = targets.shape[0]
+    if acc is None:
+        acc = torch.empty((nt, 3), dtype=torch.float64, device=targets.device)
+    if pot is None:
+        pot = torch.empty((nt,), dtype=torch.float64, device=targets.device)
+    for t in (acc, pot):
+        if not (t.is_cuda and t.is_contiguous() and t.dtype == torch.float64):
+            raise TypeError("expected contiguous float64 CUDA outputs")
+    _check(ctx, load().tree_direct(ctx, ctypes.c_void_p(targets.data_ptr()), nt, float(eps),
+                                   ctypes.c_void_p(acc.data_ptr()),
+                                   ctypes.c_void_p(pot.data_ptr()), _stream(stream)))
+    return acc, pot
+
+
 def tree_force_vjp(ctx, theta, eps, u, coef, g_pos=None, g_mass=None, stream=None):
     _check(ctx, load().tree_force_vjp(ctx, float(theta), float(eps), _ptr(u), float(coef),
                                       _ptr(g_pos), _ptr(g_mass), _stream(stream)))
@@ -267,6 +289,9 @@ class Tree:
         bh_load_state(self.ctx, buf, self.n if n is None else n)
         if n is not None:
             self.n = n
+
+    def direct(self, targets, eps):
+        return tree_direct(self.ctx, targets, eps)
 
     def force_vjp(self, theta, eps, u, coef=1.0, g_pos=None, g_mass=None):
         tree_force_vjp(self.ctx, theta, eps, u, coef, g_pos, g_mass)

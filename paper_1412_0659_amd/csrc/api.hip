@@ -56,7 +56,7 @@ void free_all(bh_ctx *c) {
     f(q.P2); f(q.size);
     Groups &g = c->groups;
     f(g.flag); f(g.scan); f(g.begin); f(g.count_dev); f(g.box); f(g.npp); f(g.npc);
-    f(c->lcell); f(c->gsrc); f(c->usort); f(c->leafof); f(c->cic);
+    f(c->lcell); f(c->gsrc); f(c->usort); f(c->leafof); f(c->cic); f(c->inv);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
 }
@@ -71,6 +71,7 @@ int check_status(bh_ctx *c) {
     BH_HIP(c, hipMemset(c->status, 0, sizeof(uint32_t)));
     if (st & kStNonFinite) return fail(c, BH_ENONFINITE, "non-finite position or velocity");
     if (st & kStMass) return fail(c, BH_EMASS, "mass <= 0 or not finite");
+    if (st & kStIndex) return fail(c, BH_EINVAL, "target index outside [0, n)");
     return fail(c, BH_ECAPACITY, "cell or stack capacity exceeded");
 }
 
@@ -196,7 +197,7 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
          dalloc(&q.P2, nc, err) && dalloc(&q.size, nc, err) && dalloc(&g.flag, n, err) &&
          dalloc(&g.scan, n, err) && dalloc(&g.begin, n + 1, err) &&
          dalloc(&g.count_dev, 1, err) && dalloc(&g.box, 2 * n, err) && dalloc(&g.npp, n, err) &&
-         dalloc(&g.npc, n, err) && dalloc(&c->cic, 65536, err);
+         dalloc(&g.npc, n, err) && dalloc(&c->cic, 65536, err) && dalloc(&c->inv, n, err);
     if (ok && prm.adjoint)
         ok = dalloc(&c->lcell, 10 * nc, err) && dalloc(&c->gsrc, 4 * n, err) &&
              dalloc(&c->usort, n, err) && dalloc(&c->leafof, n, err);
@@ -398,6 +399,19 @@ int tree_force_vjp(bh_ctx *c, float theta, float eps, const float *u, float coef
     if (!g_pos && !g_mass) return BH_OK;
     launch_walk_prep(c, theta, s);
     launch_walk_vjp(c, eps, u, coef, g_pos, g_mass, s);
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+int tree_direct(bh_ctx *c, const int64_t *targets, int64_t nt, float eps, double *acc,
+                double *pot, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!valid_eps(eps)) return fail(c, BH_EINVAL, "eps must be finite and >= 0");
+    if (nt < 0 || nt > (int64_t)UINT32_MAX / 4) return fail(c, BH_EINVAL, "bad target count");
+    if (nt && (!targets || !acc || !pot)) return fail(c, BH_EINVAL, "null pointer");
+    if (!c->built) return fail(c, BH_ESTATE, "tree_direct before tree_build");
+    if (nt == 0) return BH_OK;
+    launch_direct(c, targets, (uint32_t)nt, eps, acc, pot, s);
     BH_HIP(c, hipGetLastError());
     return BH_OK;
 }

@@ -25,6 +25,7 @@ constexpr int kStackMax = 1408;         // walk stack bound: 21 levels x 64 rang
 constexpr uint32_t kStNonFinite = 1u;
 constexpr uint32_t kStMass = 2u;
 constexpr uint32_t kStOverflow = 4u;
+constexpr uint32_t kStIndex = 8u;       // a target index outside [0, n)
 
 // Particle state in sorted (Morton) order, structure of arrays.
 struct State {
@@ -94,6 +95,7 @@ struct bh_ctx {
     float4 *usort = nullptr;   // [n] cotangent of the accelerations, sorted order
     uint32_t *leafof = nullptr;  // [n] leaf cell of each sorted particle
     double *cic = nullptr;       // [65536] accumulator of the surface-density grid
+    uint32_t *inv = nullptr;     // [n] sorted slot of each caller index (direct sum)
 
     bool built = false, have_acc = false;
     float acc_theta = 0.f, acc_eps = 0.f;
@@ -121,6 +123,12 @@ void launch_cic(const float *pos, const float *mass, const uint8_t *sel, uint32_
 void launch_cic_vjp(const float *pos, const float *mass, const uint8_t *sel, uint32_t n,
                     float rmin, float rmax, int nr, int nphi, const float *gden, float *g_pos,
                     float *g_mass, hipStream_t st);
+
+// direct.hip: FP64 direct sum at caller-index targets tgt [nt] (device)
+// into acc [nt][3] / pot [nt] (device, FP64)
+// (targets outside [0, n) are skipped and latch kStIndex)
+void launch_direct(bh_ctx *c, const int64_t *tgt, uint32_t nt, float eps, double *acc,
+                   double *pot, hipStream_t st);
 
 // keys_sort.hip
 void launch_bbox(bh_ctx *c, const State &s, uint32_t n, hipStream_t st);

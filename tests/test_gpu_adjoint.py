@@ -59,8 +59,8 @@ def test_force_vjp_matches_oracle(oracle, case):
     em = rel_err(gm1, gm_ref)
     print(f"force vjp {case}: pos med {np.median(ex):.2e} p99 {np.percentile(ex, 99):.2e}; "
           f"mass med {np.median(em):.2e} p99 {np.percentile(em, 99):.2e}")
-    assert np.median(ex) <= 2e-5 and np.percentile(ex, 99) <= 2e-4
-    assert np.median(em) <= 2e-5 and np.percentile(em, 99) <= 2e-4
+    assert np.median(ex) <= 1e-5 and np.percentile(ex, 99) <= 1e-4
+    assert np.median(em) <= 1e-5 and np.percentile(em, 99) <= 1e-4
     dd = rng.normal(size=(n, 3))
     assert abs((gp1 * dd).sum() - (gx_ref * dd).sum()) <= 1e-5 * np.abs(gx_ref * dd).sum()
 

@@ -208,23 +208,23 @@ def disk_halo_scaled(n: int, seed: int, disk_fraction: float = 0.2) -> Snapshot:
     return disk_halo(nd, n - nd, seed)
 
 
-def perturbed(s: Snapshot, seed: int, rel: float = 0.05) -> Snapshot:
-    """The same particles with every position and velocity component scaled
-    by a seeded factor 1 + rel * N(0, 1): initial conditions for a target
+def perturbed(s: Snapshot, seed: int, sigma: float = 0.02) -> Snapshot:
+    """The same particles with seeded Gaussian offsets N(0, sigma^2) added to
+    every disk position component: initial conditions for a target
     snapshot."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    fp = 1.0 + rel * rng.standard_normal(s.pos.shape)
-    fv = 1.0 + rel * rng.standard_normal(s.vel.shape)
-    return Snapshot((s.pos * fp).astype(np.float32), (s.vel * fv).astype(np.float32),
-                    s.mass.copy(), s.is_disk.copy())
+    pos = s.pos.astype(np.float64)
+    d = np.nonzero(s.is_disk)[0]
+    pos[d] += sigma * rng.standard_normal((len(d), 3))
+    return Snapshot(pos.astype(np.float32), s.vel.copy(), s.mass.copy(), s.is_disk.copy())
 
 
 # The differentiation workload: disk + halo, 64 KDK steps, the squared error
 # of the disk's face-on (R, phi) surface density against the density reached
 # from perturbed initial conditions.
 DIFF_WORKLOADS = {
-    "disk_halo_1m_adjoint": dict(n=1_000_000, seed=5, target_seed=6, eps=0.005, theta=0.4,
+    "disk_halo_1m_adjoint": dict(n=1_000_000, seed=5, target_seed=1005, eps=0.005, theta=0.4,
                                  dt=1e-3, steps=64, every=8, grid=(0.2, 4.0, 16, 32)),
-    "disk_halo_4096_adjoint": dict(n=4096, seed=7, target_seed=8, eps=0.005, theta=0.4,
+    "disk_halo_4096_adjoint": dict(n=4096, seed=5, target_seed=1005, eps=0.005, theta=0.4,
                                    dt=1e-3, steps=64, every=8, grid=(0.2, 4.0, 8, 8)),
 }
