@@ -81,6 +81,26 @@ def cpu_baseline(snap, theta, eps, budget_s=12.0):
     }
 
 
+def hbm_phases(n, ncells, ms_sort, ms_moments, pos_fp64=False):
+    """Algorithmic HBM bytes of the tree-build phases and the rate they imply.
+
+    Per particle, sort phase: box 12 B read; keys 12 B read + 12 B written
+    (u64 key, u32 index); 8 radix passes of 8 B read (digit count) + 12 B read
+    + 12 B written (scatter); gather 4 B index + 32 B state read, 32 B state +
+    16 B (x, y, z, m) record written (+48 B with the FP64 master).
+    Moments: 16 B per particle
+    read plus, per cell, 16 B of topology read, 104 B of FP64 moments written
+    and read back by the parent pass and 80 B of walk records written."""
+    gather = 4 + 32 + 32 + 16 + (48 if pos_fp64 else 0)
+    sort_b = n * (12 + 24 + 8 * 32 + gather)
+    mom_b = n * 16 + ncells * (16 + 104 + 104 + 80)
+    out = {"sort": {"bytes": sort_b, "ms": ms_sort},
+           "moments": {"bytes": mom_b, "ms": ms_moments}}
+    for v in out.values():
+        v["GBps"] = v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None
+    return out
+
+
 def _rel(a, ref):
     import numpy as np
     if a.ndim == 1:
@@ -289,6 +309,9 @@ def main(argv=None):
                      "step_events": np.mean([s["ms_step"] for s in per])},
         "tree": {"cells": last["ncells"], "leaves": last["nleaves"], "groups": last["ngroups"],
                  "depth": last["depth"]},
+        "hbm_phases": hbm_phases(snap.n, last["ncells"],
+                                 float(np.mean([s["ms_sort"] for s in per])),
+                                 float(np.mean([s["ms_moments"] for s in per]))),
         "roofline": {"bound": "alu", "achieved": walk_tflops, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": walk_tflops / PEAK_FP32_TFLOPS,
                      "traffic": load_traffic(), "kernel": "k_walk",

@@ -77,6 +77,10 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
                            "(run `python -c 'import __graft_entry__ as g; g.build()'`)")
+    # torch's HIP runtime must be the one in the process before libbh.so binds
+    # to libamdhip64.so.7: loading libbh.so first would bring in a second
+    # runtime that torch then fails to initialise its devices with.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     i64, f32, c_int = ctypes.c_int64, ctypes.c_float, ctypes.c_int
     sig = {
