@@ -203,7 +203,7 @@ def adjoint(name="disk_halo_1m_adjoint", log=print):
     finite = all(bool(torch.isfinite(a.grad).all()) for a in (x0, v0, m))
     return {"workload": name, "n": s.n, "steps": w["steps"], "checkpoint_every": w["every"],
             "theta": w["theta"], "eps": w["eps"], "dt": w["dt"], "grid": list(w["grid"]),
-            "loss": float(loss), "forward_s": fwd, "backward_s": bwd,
+            "loss": float(loss.detach()), "forward_s": fwd, "backward_s": bwd,
             "backward_over_forward": bwd / fwd,
             "ms_per_step_forward": 1e3 * fwd / w["steps"],
             "ms_per_step_backward": 1e3 * bwd / w["steps"], "grad_finite": finite}
@@ -218,6 +218,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only run the differentiation workload and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy five times (the "
                          "reference kernel for scaling the HBM byte counters)")
@@ -245,9 +247,13 @@ def main(argv=None):
                           "launches": 5}))
         return 0
 
+    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    if args.adjoint_only:
+        print(json.dumps(adjoint(log=log)))
+        return 0
+
     w = ics.WORKLOADS[args.workload]
     theta, eps, dt = w["theta"], w["eps"], w.get("dt", 1e-3)
-    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
     t0 = time.perf_counter()
     snap = ics.make(args.workload)
     log(f"[bench] workload {args.workload} n={snap.n} generated in {time.perf_counter() - t0:.1f} s")
