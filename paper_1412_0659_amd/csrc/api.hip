@@ -84,6 +84,7 @@ void rebuild(bh_ctx *c, uint32_t n, hipStream_t s) {
     (void)hipEventRecord(c->ev[1], s);
     launch_build(c, n, s);
     launch_groups(c, n, s);
+    launch_count_leaves(c, s);
     (void)hipEventRecord(c->ev[2], s);
     launch_moments(c, s);
     (void)hipEventRecord(c->ev[3], s);
@@ -185,7 +186,7 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
     ok = ok && dalloc(&c->acc, n, err) && dalloc(&c->xyzm, n, err) &&
          dalloc(&c->spill, (size_t)c->walk_grid * kStackMax, err) && dalloc(&c->box, 8, err) &&
          dalloc(&c->box_part, 6 * 1024, err) && dalloc(&c->status, 4, err) &&
-         dalloc(&c->work, 8, err) && dalloc(&c->totals, 2, err) &&
+         dalloc(&c->work, 8, err) && dalloc(&c->totals, 4, err) &&
          dalloc(&c->sort.counts, (size_t)c->sort.counts_len, err) &&
          dalloc(&c->sort.scan_part, (size_t)c->sort.scan_part_len, err) &&
          dalloc(&q.prefix, nc, err) && dalloc(&q.level, nc, err) && dalloc(&q.begin, nc, err) &&
@@ -301,7 +302,7 @@ int bh_stats_get(bh_ctx *c, bh_stats *out, hipStream_t s) {
     out->n = c->n;
     if (c->built) {
         uint32_t ls[kLsSize], ng = 0;
-        unsigned long long tot[2] = {0, 0};
+        unsigned long long tot[3] = {0, 0, 0};
         BH_HIP(c, hipMemcpy(ls, c->cells.ls, sizeof(ls), hipMemcpyDeviceToHost));
         BH_HIP(c, hipMemcpy(&ng, c->groups.count_dev, sizeof(ng), hipMemcpyDeviceToHost));
         BH_HIP(c, hipMemcpy(tot, c->totals, sizeof(tot), hipMemcpyDeviceToHost));
@@ -313,15 +314,7 @@ int bh_stats_get(bh_ctx *c, bh_stats *out, hipStream_t s) {
             out->n_pp = (int64_t)tot[0];
             out->n_pc = (int64_t)tot[1];
         }
-        // leaves: cells with no children
-        uint32_t *nch = new (std::nothrow) uint32_t[out->ncells > 0 ? out->ncells : 1];
-        if (!nch) return fail(c, BH_ENOMEM, "host allocation");
-        hipError_t e = hipMemcpy(nch, c->cells.nchild, sizeof(uint32_t) * out->ncells,
-                                 hipMemcpyDeviceToHost);
-        if (e == hipSuccess)
-            for (int64_t i = 0; i < out->ncells; ++i) out->nleaves += nch[i] == 0;
-        delete[] nch;
-        BH_HIP(c, e);
+        out->nleaves = (int64_t)tot[2];  // counted on the device by the build
     }
     out->ms_sort = elapsed(c, 0, 1);
     out->ms_build = elapsed(c, 1, 2);

@@ -84,7 +84,7 @@ struct bh_ctx {
     float *box_part = nullptr;
     uint32_t *status = nullptr;
     uint32_t *work = nullptr;                // [8] walk work counters
-    unsigned long long *totals = nullptr;    // [2] n_pp, n_pc
+    unsigned long long *totals = nullptr;    // [4] n_pp, n_pc, leaves
     bh::Sort sort{};
     bh::Cells cells{};
     bh::Groups groups{};
@@ -162,6 +162,7 @@ void launch_kick_drift(bh_ctx *c, float h, float dt, uint32_t n, hipStream_t st)
 void launch_unsort(bh_ctx *c, float *acc, float *pot, uint32_t n, hipStream_t st);
 void launch_state_out(bh_ctx *c, float *pos, float *vel, uint32_t n, hipStream_t st);
 void launch_totals(bh_ctx *c, uint32_t n, hipStream_t st);
+void launch_count_leaves(bh_ctx *c, hipStream_t st);
 void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }

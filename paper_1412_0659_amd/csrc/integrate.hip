@@ -176,6 +176,26 @@ __global__ __launch_bounds__(256) void k_totals(const uint32_t *__restrict__ gbe
     }
 }
 
+// number of leaf cells of the tree into tot[2]
+__global__ __launch_bounds__(256) void k_count_leaves(Cells c, unsigned long long *tot) {
+    const uint32_t nc = c.ls[kLevels];
+    unsigned long long k = 0;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256)
+        k += c.nchild[i] == 0u;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) k += __shfl_xor(k, d, 64);
+    if (lane_id() == 0) atomicAdd(&tot[2], k);
+}
+
+__global__ void k_zero_leaves(unsigned long long *tot) {
+    if (threadIdx.x == 0) tot[2] = 0ull;
+}
+
+void launch_count_leaves(bh_ctx *c, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_leaves, dim3(1), dim3(64), 0, st, c->totals);
+    hipLaunchKernelGGL(k_count_leaves, dim3(512), dim3(256), 0, st, c->cells, c->totals);
+}
+
 __global__ void k_zero_totals(unsigned long long *tot) {
     if (threadIdx.x < 2) tot[threadIdx.x] = 0ull;
 }
