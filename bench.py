@@ -318,6 +318,10 @@ def main(argv=None):
         "hbm_phases": hbm_phases(snap.n, last["ncells"],
                                  float(np.mean([s["ms_sort"] for s in per])),
                                  float(np.mean([s["ms_moments"] for s in per]))),
+        "paper_context": {"hardware": "NVIDIA K20X, the paper's 1-GPU column (Table II)",
+                          "workload": "the paper's Milky Way model, 13M particles, theta 0.4",
+                          "gravity_interactions_per_s": 3.33e10, "gravity_tflops": 1.77,
+                          "note": "another machine and another model: context, not a baseline"},
         "roofline": {"bound": "alu", "achieved": walk_tflops, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": walk_tflops / PEAK_FP32_TFLOPS,
                      "traffic": load_traffic(), "kernel": "k_walk",

@@ -200,7 +200,7 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
          dalloc(&g.count_dev, 1, err) && dalloc(&g.box, 2 * n, err) && dalloc(&g.npp, n, err) &&
          dalloc(&g.npc, n, err) && dalloc(&c->cic, 65536, err) && dalloc(&c->inv, n, err);
     if (ok && prm.adjoint)
-        ok = dalloc(&c->lcell, 10 * nc, err) && dalloc(&c->gsrc, 4 * n, err) &&
+        ok = dalloc(&c->lcell, 8 * 10 * nc, err) && dalloc(&c->gsrc, 8 * 4 * n, err) &&
              dalloc(&c->usort, n, err) && dalloc(&c->leafof, n, err);
     for (auto &e : c->ev)
         if (ok && hipEventCreate(&e) != hipSuccess) ok = false;

@@ -90,8 +90,10 @@ struct bh_ctx {
     bh::Groups groups{};
 
     // adjoint buffers (contexts created with adjoint = 1)
-    double *lcell = nullptr;   // [cells][10]: dL/dM, dL/dcom xyz, dL/dQ xx yy zz xy xz yz
-    double *gsrc = nullptr;    // [n][4]: dL/dx xyz, dL/dm of sorted particles
+    // per-XCD copies (8): [8][cap_cells][10] dL/dM, dL/dcom xyz, dL/dQ xx yy zz xy xz yz;
+    // [8][n_max][4] dL/dx xyz, dL/dm of sorted particles
+    double *lcell = nullptr;
+    double *gsrc = nullptr;
     float4 *usort = nullptr;   // [n] cotangent of the accelerations, sorted order
     uint32_t *leafof = nullptr;  // [n] leaf cell of each sorted particle
     double *cic = nullptr;       // [65536] accumulator of the surface-density grid

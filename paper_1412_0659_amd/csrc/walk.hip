@@ -95,15 +95,17 @@ __device__ __forceinline__ h2 hsplat(float v) {
     const _Float16 h = (_Float16)v;
     return h2{h, h};
 }
+__device__ __forceinline__ h2 as_h2(uint32_t u) { return __builtin_bit_cast(h2, u); }
 
-// staged FP16 record of cell k (a pair (2p, 2p+1) is read as one h2)
+// Pair record of cells (2p, 2p+1) of a chunk: 13 FP16x2 fields (low half =
+// cell 2p), then the FP32 factors M s^2 and M s of both cells; 20 dwords so
+// that it is read with four 16-byte loads and one 4-byte load.
 enum { kDx, kDy, kDz, kRho, kE2, kBxx, kByy, kBzz, kBxy, kBxz, kByz, kHtr, kCtr, kH };
+constexpr int kFa = kH, kFphi = kH + 2, kRec = 20;
 constexpr int kNullPair = kChunk / 2;
 
 struct Far16Lds {
-    _Float16 h[kH][kChunk + 2];
-    float fa[kChunk + 2];    // M s^2
-    float fphi[kChunk + 2];  // M s
+    uint32_t rec[kChunk / 2 + 1][kRec];
 };
 
 struct WalkLds {
@@ -121,44 +123,43 @@ struct Phase {
     h2 ti[3];  // FP16 far field: (x_i - gc) s_g, both halves equal
 };
 
-__device__ __forceinline__ h2 hpair(const Far16Lds &S, int f, uint32_t p) {
-    return reinterpret_cast<const h2 *>(S.h[f])[p];
-}
-
 // One pair of particle-cell terms in FP16 (cells 2p and 2p+1 of the chunk).
 __device__ __forceinline__ void pc16_pair(const h2 ti[3], const Far16Lds &S, uint32_t p,
                                           float4 &acc) {
-    const h2 rho = hpair(S, kRho, p);
-    const h2 dx = hfma(-rho, ti[0], hpair(S, kDx, p));
-    const h2 dy = hfma(-rho, ti[1], hpair(S, kDy, p));
-    const h2 dz = hfma(-rho, ti[2], hpair(S, kDz, p));
-    const h2 r2 = hfma(dx, dx, hfma(dy, dy, hfma(dz, dz, hpair(S, kE2, p))));
+    const uint4 *R = reinterpret_cast<const uint4 *>(S.rec[p]);
+    const uint4 q0 = R[0], q1 = R[1], q2 = R[2], q3 = R[3];
+    const float fphi1 = __builtin_bit_cast(float, S.rec[p][kFphi + 1]);
+    const h2 rho = as_h2(q0.w);
+    const h2 dx = hfma(-rho, ti[0], as_h2(q0.x));
+    const h2 dy = hfma(-rho, ti[1], as_h2(q0.y));
+    const h2 dz = hfma(-rho, ti[2], as_h2(q0.z));
+    const h2 r2 = hfma(dx, dx, hfma(dy, dy, hfma(dz, dz, as_h2(q1.x))));
     h2 ri;
     ri.x = __builtin_amdgcn_rsqh(r2.x);
     ri.y = __builtin_amdgcn_rsqh(r2.y);
     const h2 ri2 = ri * ri, ri3 = ri * ri2, ri5 = ri3 * ri2;
-    const h2 bxx = hpair(S, kBxx, p), byy = hpair(S, kByy, p), bzz = hpair(S, kBzz, p);
-    const h2 bxy = hpair(S, kBxy, p), bxz = hpair(S, kBxz, p), byz = hpair(S, kByz, p);
+    const h2 bxx = as_h2(q1.y), byy = as_h2(q1.z), bzz = as_h2(q1.w);
+    const h2 bxy = as_h2(q2.x), bxz = as_h2(q2.y), byz = as_h2(q2.z);
     const h2 qx = hfma(bxx, dx, hfma(bxy, dy, bxz * dz));
     const h2 qy = hfma(bxy, dx, hfma(byy, dy, byz * dz));
     const h2 qz = hfma(bxz, dx, hfma(byz, dy, bzz * dz));
     const h2 dq = hfma(dx, qx, hfma(dy, qy, dz * qz));
     const h2 a5 = dq * ri5;
-    h2 ph = hfma(hpair(S, kHtr, p), ri3, -ri);
+    h2 ph = hfma(as_h2(q2.w), ri3, -ri);
     ph = hfma(hsplat(0.5f), a5, ph);
     const h2 u = hfma(hsplat(-2.5f), a5, ri);
-    const h2 s = hfma(hpair(S, kCtr, p), ri5, u * ri2);
+    const h2 s = hfma(as_h2(q3.x), ri5, u * ri2);
     const h2 ax = hfma(s, dx, qx * ri5), ay = hfma(s, dy, qy * ri5), az = hfma(s, dz, qz * ri5);
-    const float2 fa = reinterpret_cast<const float2 *>(S.fa)[p];
-    const float2 fp = reinterpret_cast<const float2 *>(S.fphi)[p];
-    acc.x = fmaf((float)ax.x, fa.x, acc.x);
-    acc.x = fmaf((float)ax.y, fa.y, acc.x);
-    acc.y = fmaf((float)ay.x, fa.x, acc.y);
-    acc.y = fmaf((float)ay.y, fa.y, acc.y);
-    acc.z = fmaf((float)az.x, fa.x, acc.z);
-    acc.z = fmaf((float)az.y, fa.y, acc.z);
-    acc.w = fmaf((float)ph.x, fp.x, acc.w);
-    acc.w = fmaf((float)ph.y, fp.y, acc.w);
+    const float fa0 = __builtin_bit_cast(float, q3.y), fa1 = __builtin_bit_cast(float, q3.z);
+    const float fphi0 = __builtin_bit_cast(float, q3.w);
+    acc.x = fmaf((float)ax.x, fa0, acc.x);
+    acc.x = fmaf((float)ax.y, fa1, acc.x);
+    acc.y = fmaf((float)ay.x, fa0, acc.y);
+    acc.y = fmaf((float)ay.y, fa1, acc.y);
+    acc.z = fmaf((float)az.x, fa0, acc.z);
+    acc.z = fmaf((float)az.y, fa1, acc.z);
+    acc.w = fmaf((float)ph.x, fphi0, acc.w);
+    acc.w = fmaf((float)ph.y, fphi1, acc.w);
 }
 
 // Evaluate n staged pairs for one phase (null pair past the end).
@@ -170,19 +171,20 @@ __device__ __forceinline__ void eval16_chunk(Phase &ph, uint32_t n, const Far16L
     if (rem) pc16_pair(ph.ti, S, ph.slice < rem ? k : (uint32_t)kNullPair, ph.acc);
 }
 
-// Write the FP16 record of one cell (or a null record) into slot k.
+// Write the FP16 half-record of cell k of the chunk (a far cell, or a hole
+// that contributes nothing when !valid).  s = 2^-e scales the (group, cell)
+// pair, eg the group; Q^ = Q s^2 / M uses an approximate 1/M (the FP16
+// rounding dominates its error).
 __device__ __forceinline__ void stage16(Far16Lds &S, uint32_t k, bool valid, const float4 &A,
-                                        const float4 &B, const float4 &C, float gcx, float gcy,
-                                        float gcz, float ghmax, int eg, float eps2) {
+                                        const float4 &B, const float4 &C, float cx, float cy,
+                                        float cz, int e, int eg, float eps2) {
     float v[kH], fa = 0.f, fp = 0.f;
+#pragma unroll
     for (int f = 0; f < kH; ++f) v[f] = 0.f;
     v[kDx] = 1.f;
     if (valid) {
-        const float cx = A.x - gcx, cy = A.y - gcy, cz = A.z - gcz;
-        const float L = fmaxf(fmaxf(fabsf(cx), fabsf(cy)), fabsf(cz)) + ghmax;
-        const int e = __builtin_amdgcn_frexp_expf(L);
         const float s = ldexpf(1.f, -e);
-        const float k2 = s * s / A.w;
+        const float k2 = s * s * __builtin_amdgcn_rcpf(A.w);
         v[kDx] = cx * s; v[kDy] = cy * s; v[kDz] = cz * s;
         v[kRho] = ldexpf(1.f, min(eg - e, 14));
         v[kE2] = fminf(eps2 * s * s, 6.0e4f);
@@ -192,9 +194,12 @@ __device__ __forceinline__ void stage16(Far16Lds &S, uint32_t k, bool valid, con
         fa = A.w * s * s;
         fp = A.w * s;
     }
-    for (int f = 0; f < kH; ++f) S.h[f][k] = (_Float16)v[f];
-    S.fa[k] = fa;
-    S.fphi[k] = fp;
+    uint32_t *rec = S.rec[k >> 1];
+    _Float16 *h = reinterpret_cast<_Float16 *>(rec) + (k & 1u);
+#pragma unroll
+    for (int f = 0; f < kH; ++f) h[2 * f] = (_Float16)v[f];
+    rec[kFa + (k & 1u)] = __builtin_bit_cast(uint32_t, fa);
+    rec[kFphi + (k & 1u)] = __builtin_bit_cast(uint32_t, fp);
 }
 
 // Evaluate n (<= 64) staged sources for one phase; entries past n read the
@@ -204,9 +209,20 @@ __device__ __forceinline__ void eval_chunk(Phase &ph, uint32_t n, const WalkLds 
     const uint32_t r = ph.r;
     const uint32_t full = n / r, rem = n - full * r;
     uint32_t k = ph.slice;
-    for (uint32_t j = 0; j < full; ++j, k += r) {
+    uint32_t j = 0;
+    for (; j + 1u < full; j += 2u, k += 2u * r) {  // two sources per trip
+        if (kIsPc) {
+            pc_term(ph.tgt, L.stage[0][k], L.stage[1][k], L.stage[2][k], eps2, ph.acc);
+            pc_term(ph.tgt, L.stage[0][k + r], L.stage[1][k + r], L.stage[2][k + r], eps2, ph.acc);
+        } else {
+            pp_term<kEps0>(ph.tgt, L.stage[0][k], eps2, ph.acc);
+            pp_term<kEps0>(ph.tgt, L.stage[0][k + r], eps2, ph.acc);
+        }
+    }
+    if (j < full) {
         if (kIsPc) pc_term(ph.tgt, L.stage[0][k], L.stage[1][k], L.stage[2][k], eps2, ph.acc);
         else pp_term<kEps0>(ph.tgt, L.stage[0][k], eps2, ph.acc);
+        k += r;
     }
     if (rem) {
         const uint32_t kk = ph.slice < rem ? k : (uint32_t)kNull;
@@ -260,19 +276,20 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
         p2.ti[2] = hsplat((p2.tgt.z - b.cz) * sg);
     }
 
-    if (lane == 0) {
-        L.stage[0][kNull] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
-        L.stage[1][kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
-        L.stage[2][kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    if (kF16 && lane < 2) {
-        const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
-        stage16(S, kChunk + lane, false, z4, z4, z4, 0.f, 0.f, 0.f, 0.f, 0, 0.f);
-    }
+    // the null source of the FP32 staging area (rewritten by every flush: in
+    // the FP16 walk the pair records share that area)
+    auto put_null = [&]() {
+        if (lane == 0) {
+            L.stage[0][kNull] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+            L.stage[1][kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
+            L.stage[2][kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
 
     // evaluate the particle-cell list: stage 64 records at a time, loading
     // the next chunk while the current one is evaluated
     auto flush_pc32 = [&](uint32_t n) {
+        put_null();
         float4 r0, r1, r2;
         {
             const uint32_t c = L.T.pcidx[lane < n ? lane : 0u];
@@ -294,34 +311,37 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
         __syncthreads();
     };
     // FP16 far field: each chunk is staged as FP16 pair records; cells too
-    // close to the group for FP16 are compacted into the FP32 staging area
+    // close to the group for FP16 leave a hole and their indices are moved
+    // to the front of the list (positions already consumed), to be
+    // evaluated in FP32, in full chunks, after the far cells
     auto flush_pc16 = [&](uint32_t n) {
+        if (lane < 2) {  // the null pair
+            const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+            stage16(S, kChunk + lane, false, z4, z4, z4, 0.f, 0.f, 0.f, 0, 0, 0.f);
+        }
         float4 r0, r1, r2;
         {
             const uint32_t c = L.T.pcidx[lane < n ? lane : 0u];
             r0 = a.P0[c]; r1 = a.P1[c]; r2 = a.P2[c];
         }
+        uint32_t nnear = 0;
         for (uint32_t base = 0; base < n; base += kChunk) {
             const uint32_t m = n - base < (uint32_t)kChunk ? n - base : (uint32_t)kChunk;
             const bool valid = lane < m;
-            bool near = false;
-            {
-                const float cx = r0.x - b.cx, cy = r0.y - b.cy, cz = r0.z - b.cz;
-                const float bx = fmaxf(fabsf(cx) - b.hx, 0.f), by = fmaxf(fabsf(cy) - b.hy, 0.f),
-                            bz = fmaxf(fabsf(cz) - b.hz, 0.f);
-                const float d = sqrtf(bx * bx + by * by + bz * bz);
-                const float Lc = fmaxf(fmaxf(fabsf(cx), fabsf(cy)), fabsf(cz)) + ghmax;
-                const float sc = ldexpf(1.f, -(__builtin_amdgcn_frexp_expf(Lc)));
-                near = valid && !(d * sc >= 0.25f);
-            }
+            const uint32_t cidx = L.T.pcidx[base + (valid ? lane : 0u)];
+            const float cx = r0.x - b.cx, cy = r0.y - b.cy, cz = r0.z - b.cz;
+            const float Lc = fmaxf(fmaxf(fabsf(cx), fabsf(cy)), fabsf(cz)) + ghmax;
+            const int e = __builtin_amdgcn_frexp_expf(Lc);
+            const float bx = fmaxf(fabsf(cx) - b.hx, 0.f), by = fmaxf(fabsf(cy) - b.hy, 0.f),
+                        bz = fmaxf(fabsf(cz) - b.hz, 0.f);
+            // near: box distance d with d s < 1/4, i.e. d^2 < 2^(2e - 4)
+            const float d2 = fmaf(bx, bx, fmaf(by, by, bz * bz));
+            const bool near = valid && !(d2 >= ldexpf(1.f, 2 * e - 4));
             __syncthreads();
-            stage16(S, lane, valid && !near, r0, r1, r2, b.cx, b.cy, b.cz, ghmax, eg, a.eps2);
+            stage16(S, lane, valid && !near, r0, r1, r2, cx, cy, cz, e, eg, a.eps2);
             const uint64_t nm = ballot(near);
-            if (near) {
-                const uint32_t slot = count_below(nm);
-                L.stage[0][slot] = r0; L.stage[1][slot] = r1; L.stage[2][slot] = r2;
-            }
-            const uint32_t nn = (uint32_t)__popcll(nm);
+            if (near) L.T.pcidx[nnear + count_below(nm)] = cidx;
+            nnear += (uint32_t)__popcll(nm);
             __syncthreads();
             if (base + kChunk < n) {
                 const uint32_t q = base + kChunk + lane;
@@ -331,18 +351,16 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
             const uint32_t np = (m + 1u) >> 1;
             eval16_chunk(p1, np, S);
             if (two) eval16_chunk(p2, np, S);
-            if (nn) {
-                eval_chunk<true, kEps0>(p1, nn, L, a.eps2);
-                if (two) eval_chunk<true, kEps0>(p2, nn, L, a.eps2);
-            }
         }
         __syncthreads();
+        if (nnear) flush_pc32(nnear);
     };
     auto flush_pc = [&](uint32_t n) {
         if (kF16) flush_pc16(n);
         else flush_pc32(n);
     };
     auto flush_pp = [&](uint32_t n) {
+        put_null();
         float4 r0 = a.xyzm[L.T.ppidx[lane < n ? lane : 0u]];
         for (uint32_t base = 0; base < n; base += kChunk) {
             const uint32_t m = n - base < (uint32_t)kChunk ? n - base : (uint32_t)kChunk;
@@ -405,13 +423,10 @@ __device__ __forceinline__ void walk_loop(const WalkArgs &a, WalkLds &L, Far16Ld
 template <bool kEps0, bool kF16>
 __global__ __launch_bounds__(64) void k_walk(WalkArgs a) {
     __shared__ WalkLds L;
-    if constexpr (kF16) {
-        __shared__ Far16Lds S;
-        walk_loop<kEps0, true>(a, L, S);
-    } else {
-        // the FP32 walk never touches the FP16 staging area
-        walk_loop<kEps0, false>(a, L, *reinterpret_cast<Far16Lds *>(&L));
-    }
+    // the FP16 pair records share the FP32 staging area: a flush uses one
+    // or the other, and each flush rewrites its null source
+    static_assert(sizeof(Far16Lds) <= sizeof(L.stage), "pair records exceed the staging area");
+    walk_loop<kEps0, kF16>(a, L, *reinterpret_cast<Far16Lds *>(&L.stage[0][0]));
 }
 
 __global__ void k_reset_work(uint32_t *work) {

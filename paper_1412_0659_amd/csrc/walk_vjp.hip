@@ -16,9 +16,29 @@
 // loops over the group's targets and adds the source terms to FP64
 // accumulators with one atomic per source and group.  The self pair (zero
 // separation by construction) contributes nothing.
+//
+// The accumulators come in kXcd copies, one per XCD: a wave adds into the
+// copy of the XCD it runs on (read from the hardware XCC id), with atomics
+// of workgroup scope, which that XCD's L2 executes; device-scope atomics
+// would all travel to the memory side.  Every writer of a copy shares one
+// L2, so the copy is exact; the copies are summed after the walk.
 #include "walk_common.h"
 
 namespace bh {
+
+constexpr uint32_t kXcd = 8;
+
+// XCD (XCC) that runs the calling wave.
+__device__ __forceinline__ uint32_t xcc_id() {
+    uint32_t v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & (kXcd - 1u);
+}
+
+// FP64 add executed in the L2 of the calling XCD (no return value).
+__device__ __forceinline__ void add_l2(double *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 struct VjpArgs {
     const float4 *xyzm;   // sorted positions + mass
@@ -29,7 +49,12 @@ struct VjpArgs {
     const uint32_t *gbeg, *ngroups;
     uint32_t *work, *spill, *status;
     uint32_t ring;
+    // copy 0 of kXcd accumulators; copy k at + k * lstride / gstride.  Field
+    // major: cell adjoint q of cell c at lcell[q * cap + c], particle
+    // adjoint q of particle j at gsrc[q * nmax + j], so that the lanes of one
+    // atomic instruction (neighbouring cells or particles) share cache lines
     double *lcell, *gsrc;
+    uint64_t lstride, gstride, cap, nmax;
     float eps2;
 };
 
@@ -141,6 +166,9 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
         if (lane == 0) atomicOr(a.status, kStOverflow);
         return;
     }
+    const uint32_t xcd = xcc_id();
+    double *const lcx = a.lcell + xcd * a.lstride;
+    double *const gsx = a.gsrc + xcd * a.gstride;
     const bool own = lane < gn;
     const uint32_t ti = gb + (own ? lane : 0u);
     const float4 me = a.xyzm[ti];
@@ -194,13 +222,13 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
                 for (int q = 0; q < 6; ++q) sQ[q] += gQ[q];
             }
             if (valid) {
-                double *lc = a.lcell + 10 * (size_t)c;
-                atomicAdd(lc + 0, (double)sM);
-                atomicAdd(lc + 1, (double)sw[0]);
-                atomicAdd(lc + 2, (double)sw[1]);
-                atomicAdd(lc + 3, (double)sw[2]);
+                double *lc = lcx + c;
+                add_l2(lc, (double)sM);
+                add_l2(lc + a.cap, (double)sw[0]);
+                add_l2(lc + 2 * a.cap, (double)sw[1]);
+                add_l2(lc + 3 * a.cap, (double)sw[2]);
 #pragma unroll
-                for (int q = 0; q < 6; ++q) atomicAdd(lc + 4 + q, (double)sQ[q]);
+                for (int q = 0; q < 6; ++q) add_l2(lc + (4 + q) * a.cap, (double)sQ[q]);
             }
         }
         __syncthreads();
@@ -226,11 +254,11 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
                 }
             }
             if (valid) {
-                double *gs = a.gsrc + 4 * (size_t)j;
-                atomicAdd(gs + 0, (double)sx);
-                atomicAdd(gs + 1, (double)sy);
-                atomicAdd(gs + 2, (double)sz);
-                atomicAdd(gs + 3, (double)sm);
+                double *gs = gsx + j;
+                add_l2(gs, (double)sx);
+                add_l2(gs + a.nmax, (double)sy);
+                add_l2(gs + 2 * a.nmax, (double)sz);
+                add_l2(gs + 3 * a.nmax, (double)sm);
             }
         }
         __syncthreads();
@@ -260,10 +288,10 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
             }
     }
     if (own) {
-        double *gs = a.gsrc + 4 * (size_t)ti;
-        atomicAdd(gs + 0, (double)rx);
-        atomicAdd(gs + 1, (double)ry);
-        atomicAdd(gs + 2, (double)rz);
+        double *gs = gsx + ti;
+        add_l2(gs, (double)rx);
+        add_l2(gs + a.nmax, (double)ry);
+        add_l2(gs + 2 * a.nmax, (double)rz);
     }
     __syncthreads();
 }
@@ -297,11 +325,38 @@ __global__ __launch_bounds__(256) void k_usort(const float *__restrict__ u,
     us[i] = make_float4(u[3 * p], u[3 * p + 1], u[3 * p + 2], 0.f);
 }
 
-__global__ __launch_bounds__(256) void k_fill_f64(double *p, uint64_t n) {
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-         i += (uint64_t)gridDim.x * 256)
-        p[i] = 0.0;
+// Zero the kXcd copies of F fields of cnt entries each (field q at q * fs;
+// cnt = the cell count of the current tree when ls is given).
+__global__ __launch_bounds__(256) void k_zero_xcd(double *p, uint64_t cnt, uint32_t F,
+                                                  uint64_t fs, uint64_t stride,
+                                                  const uint32_t *ls) {
+    if (ls) cnt = ls[kLevels];
+    const uint64_t total = cnt * F;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * 256) {
+        const uint64_t q = i / cnt, e = i - q * cnt;
+#pragma unroll
+        for (uint32_t k = 0; k < kXcd; ++k) p[q * fs + e + k * stride] = 0.0;
+    }
 }
+
+
+// Fold the kXcd copies (same layout as k_zero_xcd) into copy 0.
+__global__ __launch_bounds__(256) void k_fold_xcd(double *p, uint64_t cnt, uint32_t F,
+                                                  uint64_t fs, uint64_t stride,
+                                                  const uint32_t *ls) {
+    if (ls) cnt = ls[kLevels];
+    const uint64_t total = cnt * F;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * 256) {
+        const uint64_t q = i / cnt, e = i - q * cnt, o = q * fs + e;
+        double v = p[o];
+#pragma unroll
+        for (uint32_t k = 1; k < kXcd; ++k) v += p[o + k * stride];
+        p[o] = v;
+    }
+}
+
 
 // Each particle adds the adjoints of the cells holding it (its leaf and the
 // leaf's ancestors), then the total is scaled and added to the caller-order
@@ -310,18 +365,19 @@ __global__ __launch_bounds__(256) void k_moments_vjp(Cells c, const float4 *__re
                                                      const uint32_t *__restrict__ leafof,
                                                      const uint32_t *__restrict__ cid,
                                                      const double *__restrict__ lcell,
-                                                     const double *__restrict__ gsrc, uint32_t n,
+                                                     const double *__restrict__ gsrc,
+                                                     uint64_t cap, uint64_t nmax, uint32_t n,
                                                      float coef, float *g_pos, float *g_mass) {
     const uint32_t k = blockIdx.x * 256 + threadIdx.x;
     if (k >= n) return;
     const float4 p = xyzm[k];
     const double xk = p.x, yk = p.y, zk = p.z, mk = p.w;
-    double gx = gsrc[4 * (size_t)k], gy = gsrc[4 * (size_t)k + 1], gz = gsrc[4 * (size_t)k + 2];
-    double gm = gsrc[4 * (size_t)k + 3];
+    double gx = gsrc[k], gy = gsrc[k + nmax], gz = gsrc[k + 2 * nmax], gm = gsrc[k + 3 * nmax];
     for (uint32_t cc = leafof[k]; cc != kNone; cc = c.parent[cc]) {
-        const double *l = lcell + 10 * (size_t)cc;
-        const double lM = l[0], lx = l[1], ly = l[2], lz = l[3];
-        const double qxx = l[4], qyy = l[5], qzz = l[6], qxy = l[7], qxz = l[8], qyz = l[9];
+        const double *l = lcell + cc;
+        const double lM = l[0], lx = l[cap], ly = l[2 * cap], lz = l[3 * cap];
+        const double qxx = l[4 * cap], qyy = l[5 * cap], qzz = l[6 * cap], qxy = l[7 * cap],
+                     qxz = l[8 * cap], qyz = l[9 * cap];
         const double M = c.M[cc];
         const double sx = xk - c.com[3 * (size_t)cc], sy = yk - c.com[3 * (size_t)cc + 1],
                      sz = zk - c.com[3 * (size_t)cc + 2];
@@ -354,9 +410,13 @@ void launch_walk_vjp(bh_ctx *c, float eps, const float *u, float coef, float *g_
     const uint32_t n = (uint32_t)c->n;
     const uint32_t nb = cdiv(n, 256);
     const uint32_t grid = nb < 4096u ? (nb ? nb : 1u) : 4096u;
-    hipLaunchKernelGGL(k_fill_f64, dim3(4096), dim3(256), 0, st, c->lcell,
-                       (uint64_t)10 * (uint64_t)c->cap_cells);
-    hipLaunchKernelGGL(k_fill_f64, dim3(grid), dim3(256), 0, st, c->gsrc, (uint64_t)4 * n);
+    const uint64_t cap = (uint64_t)c->cap_cells, nmax = (uint64_t)c->nmax;
+    const uint64_t lstride = 10ull * cap, gstride = 4ull * nmax;
+    const uint32_t *ls = c->cells.ls;
+    hipLaunchKernelGGL(k_zero_xcd, dim3(2048), dim3(256), 0, st, c->lcell, (uint64_t)0, 10u, cap,
+                       lstride, ls);
+    hipLaunchKernelGGL(k_zero_xcd, dim3(grid), dim3(256), 0, st, c->gsrc, (uint64_t)n, 4u, nmax,
+                       gstride, (const uint32_t *)nullptr);
     hipLaunchKernelGGL(k_leafof, dim3(kGrid * 2), dim3(256), 0, st, c->cells, c->leafof);
     hipLaunchKernelGGL(k_usort, dim3(nb), dim3(256), 0, st, u,
                        (const uint32_t *)c->st[c->cur].cid, n, c->usort);
@@ -368,16 +428,22 @@ void launch_walk_vjp(bh_ctx *c, float eps, const float *u, float coef, float *g_
     a.work = c->work; a.spill = c->spill; a.status = c->status;
     a.ring = c->walk_small_stack ? 128u : (uint32_t)kRing;
     a.lcell = c->lcell; a.gsrc = c->gsrc;
+    a.lstride = lstride; a.gstride = gstride;
+    a.cap = cap; a.nmax = nmax;
     a.eps2 = eps * eps;
     hipLaunchKernelGGL(k_reset_work_vjp, dim3(1), dim3(64), 0, st, c->work);
     if (eps == 0.f)
         hipLaunchKernelGGL(k_walk_vjp<true>, dim3(c->walk_grid), dim3(64), 0, st, a);
     else
         hipLaunchKernelGGL(k_walk_vjp<false>, dim3(c->walk_grid), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_fold_xcd, dim3(2048), dim3(256), 0, st, c->lcell, (uint64_t)0, 10u, cap,
+                       lstride, ls);
+    hipLaunchKernelGGL(k_fold_xcd, dim3(grid), dim3(256), 0, st, c->gsrc, (uint64_t)n, 4u, nmax,
+                       gstride, (const uint32_t *)nullptr);
     hipLaunchKernelGGL(k_moments_vjp, dim3(nb), dim3(256), 0, st, c->cells,
                        (const float4 *)c->xyzm, (const uint32_t *)c->leafof,
                        (const uint32_t *)c->st[c->cur].cid, (const double *)c->lcell,
-                       (const double *)c->gsrc, n, coef, g_pos, g_mass);
+                       (const double *)c->gsrc, cap, nmax, n, coef, g_pos, g_mass);
 }
 
 // y += a x over n [3]-vectors (the drift's transpose in the adjoint step)
