@@ -121,10 +121,10 @@ def _timed_force(tree, theta, eps, reps):
     return (sum(ms) / len(ms), acc.double().cpu().numpy(), pot.double().cpu().numpy(), st)
 
 
-def precision(snap, theta, eps, nsample=65536, seed=40, reps=3, log=print):
+def precision(snap, theta, eps, nsample=65536, seed=40, reps=3, log=print, ref=None):
     """Plain FP32 walk vs the FP16 far-field walk on the same particles: walk
     time and force error against the GPU's FP64 direct sum at a seeded
-    uniform subsample of targets."""
+    uniform subsample of targets (ref: that direct sum, if already taken)."""
     import numpy as np
     import torch
 
@@ -138,7 +138,6 @@ def precision(snap, theta, eps, nsample=65536, seed=40, reps=3, log=print):
     out = {"theta": theta, "eps": eps,
            "sample": f"{len(idx)} targets, seeded uniform subsample (seed {seed}) of "
                      f"{snap.n}; reference: FP64 direct sum on the GPU (tree_direct)"}
-    ref = None
     for name, f16 in (("fp32", False), ("fp16_far", True)):
         tree = bh.Tree(snap.n, far_fp16=f16)
         tree.build(pos, mass)
@@ -161,7 +160,22 @@ def precision(snap, theta, eps, nsample=65536, seed=40, reps=3, log=print):
         log(f"[bench] precision {name}: walk {ms:.2f} ms, acc err median "
             f"{out[name]['err_acc_median']:.2e} p99 {out[name]['err_acc_p99']:.2e}")
     out["speedup_walk_fp16_far"] = out["fp32"]["walk_ms"] / out["fp16_far"]["walk_ms"]
+    out["_ref"] = ref
     return out
+
+
+def precision_sweep(name="disk_halo_4m", thetas=(0.3, 0.4, 0.6), log=print):
+    """The precision form's table: FP32 and FP16 far-field walks at several
+    opening angles, errors against one FP64 direct sum."""
+    from workloads import ics
+    w = ics.WORKLOADS[name]
+    snap = ics.make(name)
+    rows, ref = [], None
+    for th in thetas:
+        r = precision(snap, th, w["eps"], log=log, ref=ref)
+        ref = r.pop("_ref")
+        rows.append(r)
+    return {"workload": name, "n": snap.n, "eps": w["eps"], "rows": rows}
 
 
 def adjoint(name="disk_halo_1m_adjoint", log=print):
@@ -218,6 +232,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--precision-sweep", action="store_true",
+                    help="only run the precision form's table (4M disk + halo, theta 0.3/0.4/0.6)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the differentiation workload and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -250,6 +266,9 @@ def main(argv=None):
     log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
     if args.adjoint_only:
         print(json.dumps(adjoint(log=log)))
+        return 0
+    if args.precision_sweep:
+        print(json.dumps(precision_sweep(log=log)))
         return 0
 
     w = ics.WORKLOADS[args.workload]
@@ -331,6 +350,7 @@ def main(argv=None):
     del pos, vel, mass
     if not args.no_precision:
         out["precision"] = precision(snap, theta, eps, log=log)
+        out["precision"].pop("_ref")
     if not args.no_adjoint:
         out["adjoint"] = adjoint(log=log)
     if not args.no_cpu_baseline:

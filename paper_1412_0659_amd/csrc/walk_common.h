@@ -116,7 +116,7 @@ __device__ __forceinline__ void traverse(const TreeView &tv, const GroupBox &b, 
         const uint32_t incl = wave_incl_scan(ne, lane);
         const uint32_t excl = incl - ne;
         const uint32_t nfull = (uint32_t)__popcll(ballot(lane < avail && incl <= 64u));
-        const uint32_t tall = shfl(incl, (int)avail - 1);
+        const uint32_t tall = read_lane(incl, avail - 1u);
         const uint32_t total = tall < 64u ? tall : 64u;
         L.starts[lane] = 0u;
         __syncthreads();
@@ -180,7 +180,7 @@ __device__ __forceinline__ void traverse(const TreeView &tv, const GroupBox &b, 
         // ---- particles of opened leaves -> particle-particle index list
         const uint32_t lc = openleaf ? (N.y & ~kLeafBit) : 0u;
         const uint32_t lincl = wave_incl_scan(lc, lane);
-        const uint32_t P = shfl(lincl, 63);
+        const uint32_t P = read_lane(lincl, 63u);
         if (P > 0u) {
             L.offs[lane] = lincl - lc;
             L.firsts[lane] = N.x;

@@ -29,14 +29,24 @@ __device__ __forceinline__ uint32_t count_below(uint64_t m) {
 __device__ __forceinline__ uint32_t shfl(uint32_t v, int src) { return __shfl(v, src, 64); }
 __device__ __forceinline__ float shfl(float v, int src) { return __shfl(v, src, 64); }
 
-// inclusive prefix sum over the 64 lanes
+// inclusive prefix sum over the 64 lanes (all lanes active): a Hillis-Steele
+// scan inside each row of 16 lanes with DPP row shifts (lanes whose source is
+// outside the row add 0), then the row totals carried by the row broadcasts.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v, uint32_t lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += t;
-    }
-    return v;
+    (void)lane;
+    int s = (int)v;
+    s += __builtin_amdgcn_update_dpp(0, s, 0x111, 0xf, 0xf, false);  // row_shr:1
+    s += __builtin_amdgcn_update_dpp(0, s, 0x112, 0xf, 0xf, false);  // row_shr:2
+    s += __builtin_amdgcn_update_dpp(0, s, 0x114, 0xf, 0xf, false);  // row_shr:4
+    s += __builtin_amdgcn_update_dpp(0, s, 0x118, 0xf, 0xf, false);  // row_shr:8
+    s += __builtin_amdgcn_update_dpp(0, s, 0x142, 0xa, 0xf, false);  // row_bcast:15 -> rows 1, 3
+    s += __builtin_amdgcn_update_dpp(0, s, 0x143, 0xc, 0xf, false);  // row_bcast:31 -> rows 2, 3
+    return (uint32_t)s;
+}
+
+// value of v in lane src (src uniform across the wave)
+__device__ __forceinline__ uint32_t read_lane(uint32_t v, uint32_t src) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)src);
 }
 
 __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
