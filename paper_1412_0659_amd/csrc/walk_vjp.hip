@@ -121,6 +121,23 @@ __device__ __forceinline__ void pp_adj(const float4 &T, const float4 &U, const f
     gm = ud * ri3;
 }
 
+// Sum of v over the 64 lanes, returned uniform: DPP inclusive scan (row
+// shifts, then row broadcasts), lane 63's value read into a scalar.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ float dpp_add(float s) {
+    return s + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), kCtrl, kRowMask,
+                                                          0xf, false));
+}
+__device__ __forceinline__ float wave_total(float v) {
+    v = dpp_add<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_add<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_add<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_add<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 -> rows 1, 3
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 -> rows 2, 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 struct VjpLds {
     float4 stage[3][kChunk + 1];  // source records + the null source
     uint32_t sidx[kChunk + 1];    // particle index of staged particle sources
@@ -199,19 +216,23 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
     p2.gx = p2.gy = p2.gz = 0.f;
     const bool two = p2.T != 0u;
 
+    // particle-cell lists: lane = cell (a null cell, zero mass and moments, far
+    // away, on lanes past the list), looping over the group's targets; each
+    // pair's J^T u serves both sides: summed over targets into the cell's
+    // adjoint, and over the lanes (a DPP sum) into the target's
+    float gtx = 0.f, gty = 0.f, gtz = 0.f;  // target side of lane t's target
     auto flush_pc = [&](uint32_t n) {
         for (uint32_t base = 0; base < n; base += kChunk) {
             const uint32_t m = n - base < (uint32_t)kChunk ? n - base : (uint32_t)kChunk;
             const bool valid = lane < m;
             const uint32_t c = L.T.pcidx[base + (valid ? lane : 0u)];
-            const float4 r0 = a.P0[c], r1 = a.P1[c], r2 = a.P2[c];
-            __syncthreads();
-            L.stage[0][lane] = r0; L.stage[1][lane] = r1; L.stage[2][lane] = r2;
-            __syncthreads();
-            // pass A: target terms
-            vjp_targets<true, kEps0>(p1, m, L, a.eps2);
-            if (two) vjp_targets<true, kEps0>(p2, m, L, a.eps2);
-            // pass B: this lane's cell over all targets of the group
+            float4 r0 = make_float4(1e18f, 1e18f, 1e18f, 0.f), r1 = make_float4(0.f, 0.f, 0.f, 0.f),
+                   r2 = r1;
+            if (valid) {
+                r0 = a.P0[c];
+                r1 = a.P1[c];
+                r2 = a.P2[c];
+            }
             float sw[3] = {0.f, 0.f, 0.f}, sM = 0.f, sQ[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             for (uint32_t t = 0; t < gn; ++t) {
                 float wx, wy, wz, gM, gQ[6];
@@ -220,6 +241,12 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
                 sM += gM;
 #pragma unroll
                 for (int q = 0; q < 6; ++q) sQ[q] += gQ[q];
+                const float tx = wave_total(wx), ty = wave_total(wy), tz = wave_total(wz);
+                if (lane == t) {
+                    gtx -= tx;
+                    gty -= ty;
+                    gtz -= tz;
+                }
             }
             if (valid) {
                 double *lc = lcx + c;
@@ -289,9 +316,9 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
     }
     if (own) {
         double *gs = gsx + ti;
-        add_l2(gs, (double)rx);
-        add_l2(gs + a.nmax, (double)ry);
-        add_l2(gs + 2 * a.nmax, (double)rz);
+        add_l2(gs, (double)rx + (double)gtx);
+        add_l2(gs + a.nmax, (double)ry + (double)gty);
+        add_l2(gs + 2 * a.nmax, (double)rz + (double)gtz);
     }
     __syncthreads();
 }

@@ -1,0 +1,66 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the
+benchmark times (a context sized for the workload, the default walk grid).
+
+The oracle builds the whole tree from the same seeded particles (integer
+results and FP64 moments compared in full) and walks a seeded sample of
+groups; the GPU's interaction counts and forces at those groups' targets
+are compared one by one.  The precision form is checked at its 4M size
+against the oracle's direct sum at sampled targets.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import assert_tree_equal, gpu_force, gpu_tree, rel_err
+from workloads import ics
+
+pytestmark = pytest.mark.gpu
+
+MED_TOL, P99_TOL = 1e-5, 1e-4
+
+
+@pytest.mark.parametrize("name", ["disk_halo_13m", "disk_halo_1m"])
+def test_full_size_tree_and_sampled_walk(oracle, name):
+    w = ics.WORKLOADS[name]
+    s = ics.make(name)
+    print(f"case {name} n={s.n} theta={w['theta']} eps={w['eps']}", flush=True)
+    t = gpu_tree(s.pos, s.mass)
+    acc, pot = gpu_force(t, w["theta"], w["eps"])
+    ot = oracle.build_tree(s.pos, s.mass)
+    assert_tree_equal(t, ot)
+    assert np.array_equal(t.export("mom_M"), ot.mom["M"])
+    assert np.array_equal(t.export("mom_com"), ot.mom["com"])
+    assert np.array_equal(t.export("mom_Q"), ot.mom["Q"])
+    rng = np.random.default_rng(77)
+    sel = np.sort(rng.choice(ot.ngroups, size=min(3000, ot.ngroups), replace=False))
+    oacc, opot, onpp, onpc = oracle.walk(ot, w["theta"], w["eps"], groups=sel)
+    assert np.array_equal(t.export("group_npp").astype(np.int64)[sel], onpp[sel])
+    assert np.array_equal(t.export("group_npc").astype(np.int64)[sel], onpc[sel])
+    tgt = np.concatenate([ot.perm[ot.gbeg[g]:ot.gbeg[g] + ot.gcnt[g]] for g in sel])
+    ea = rel_err(acc[tgt], oacc[tgt])
+    ep = rel_err(pot[tgt], opot[tgt])
+    print(f"  {len(tgt)} targets: acc med {np.median(ea):.2e} p99 {np.percentile(ea, 99):.2e}  "
+          f"pot med {np.median(ep):.2e} p99 {np.percentile(ep, 99):.2e}", flush=True)
+    assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
+    assert np.median(ep) <= MED_TOL and np.percentile(ep, 99) <= P99_TOL
+    t.close()
+
+
+def test_precision_form_full_size(oracle):
+    """4M disk + halo, FP16 far field: at most 1e-3 median force error
+    against the FP64 direct sum at 1000 sampled targets, for each theta."""
+    w = ics.WORKLOADS["disk_halo_4m"]
+    s = ics.make("disk_halo_4m")
+    idx = ics.subsample(s.n, 1000, 40)
+    eps32 = float(np.float32(w["eps"]))
+    ra, rp = oracle.direct(s.pos, s.mass, eps32, idx)
+    for theta in (0.3, 0.4, 0.6):
+        row = []
+        for f16 in (False, True):
+            t = gpu_tree(s.pos, s.mass, far_fp16=f16)
+            acc, pot = gpu_force(t, theta, w["eps"])
+            t.close()
+            ea = rel_err(acc[idx], ra)
+            row.append((np.median(ea), np.percentile(ea, 99)))
+        print(f"  theta {theta}: FP32 tree vs direct med {row[0][0]:.2e} p99 {row[0][1]:.2e}; "
+              f"FP16 far med {row[1][0]:.2e} p99 {row[1][1]:.2e}", flush=True)
+        assert row[1][0] <= 1e-3
