@@ -243,8 +243,9 @@ def main(argv=None):
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is not part of this build)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the "
+              "library implements the single-GPU path (the domain decomposition and "
+              "tree exchange across GPUs are not implemented)", file=sys.stderr)
         return 2
 
     import numpy as np
