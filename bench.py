@@ -178,6 +178,39 @@ def precision_sweep(name="disk_halo_4m", thetas=(0.3, 0.4, 0.6), log=print):
     return {"workload": name, "n": snap.n, "eps": w["eps"], "rows": rows}
 
 
+def param_sweep(name="disk_halo_4m", thetas=(0.3, 0.4, 0.5, 0.6, 0.8),
+                leaf_crit=((16, 64), (8, 64), (32, 64), (16, 32)), reps=2, log=print):
+    """Walk cost against the opening angle (the tree-code's cost grows as
+    theta^-3) and against the leaf and group sizes, on one model."""
+    import torch
+
+    import paper_1412_0659_amd as bh
+    from workloads import ics
+    w = ics.WORKLOADS[name]
+    snap = ics.make(name)
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(snap.pos).to(dev)
+    mass = torch.from_numpy(snap.mass).to(dev)
+    rows = []
+    for nleaf, ncrit in leaf_crit:
+        tree = bh.Tree(snap.n, nleaf=nleaf, ncrit=ncrit)
+        tree.build(pos, mass)
+        st0 = tree.stats()
+        for th in (thetas if (nleaf, ncrit) == (16, 64) else (w["theta"],)):
+            ms, _, _, st = _timed_force(tree, th, w["eps"], reps)
+            inter = st["n_pp"] + st["n_pc"]
+            rows.append({"nleaf": nleaf, "ncrit": ncrit, "theta": th, "walk_ms": ms,
+                         "pp_per_particle": st["n_pp"] / snap.n,
+                         "pc_per_particle": st["n_pc"] / snap.n,
+                         "interactions_per_s": inter / (ms * 1e-3),
+                         "tflops": paper_flops(st["n_pp"], st["n_pc"]) / (ms * 1e-3) / 1e12,
+                         "cells": st0["ncells"], "groups": st0["ngroups"],
+                         "build_ms": st0["ms_sort"] + st0["ms_build"] + st0["ms_moments"]})
+            log(f"[bench] nleaf {nleaf} ncrit {ncrit} theta {th}: walk {ms:.2f} ms")
+        tree.close()
+    return {"workload": name, "n": snap.n, "eps": w["eps"], "rows": rows}
+
+
 def adjoint(name="disk_halo_1m_adjoint", log=print):
     """The differentiation workload: K KDK steps forward with checkpoints,
     surface-density loss, reverse sweep; forward and backward wall time."""
@@ -234,6 +267,8 @@ def main(argv=None):
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--precision-sweep", action="store_true",
                     help="only run the precision form's table (4M disk + halo, theta 0.3/0.4/0.6)")
+    ap.add_argument("--param-sweep", action="store_true",
+                    help="only run the walk cost sweep over theta and (nleaf, ncrit) at 4M")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the differentiation workload and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -270,6 +305,9 @@ def main(argv=None):
         return 0
     if args.precision_sweep:
         print(json.dumps(precision_sweep(log=log)))
+        return 0
+    if args.param_sweep:
+        print(json.dumps(param_sweep(log=log)))
         return 0
 
     w = ics.WORKLOADS[args.workload]

@@ -70,8 +70,9 @@ typedef struct bh_params {
     int32_t pos_fp64; /* 1: keep an FP64 master copy of the positions; the
                          leapfrog drift is done in FP64 and the tree is built
                          from its FP32 rounding.  0: FP32 positions. */
-    int32_t adjoint;  /* 1: allocate the buffers of tree_force_vjp (FP64 cell and
-                         particle adjoints, 100 bytes per cell + 40 per particle) */
+    int32_t adjoint;  /* 1: allocate the buffers of tree_force_vjp: FP64 cell and
+                         particle adjoints, one copy per XCD (8): 640 bytes per
+                         cell of capacity + 276 bytes per particle */
     int32_t reserved[3];
 } bh_params;
 
@@ -190,6 +191,19 @@ int bh_cic_density_vjp(bh_ctx *ctx, const float *pos, const float *mass, const u
 /* Copy the particle state out in caller order (device pointers, [n][3];
  * either may be NULL).  Synchronises s and reports latched device status. */
 int bh_get_state(bh_ctx *ctx, float *pos, float *vel, hipStream_t s);
+
+/* Conserved quantities of the current state in FP64 (host out[9]):
+ *   out[0]     total mass
+ *   out[1]     kinetic energy  1/2 sum m |v|^2
+ *   out[2]     potential energy 1/2 sum m phi, phi from the last force
+ *              evaluation at the current positions (self pair excluded; the
+ *              tree's potential, Sec. VI.A Eq. (1)); NaN if no force has
+ *              been computed for the current state
+ *   out[3..5]  momentum sum m v
+ *   out[6..8]  angular momentum sum m x cross v about the origin
+ * Positions are the FP64 master copy when the context keeps one.  The sums
+ * are folded in a fixed order (run to run identical).  Synchronises s. */
+int bh_diagnostics(bh_ctx *ctx, double *out, hipStream_t s);
 
 /* Wait for s and return the latched device status (BH_OK if clean). */
 int bh_sync(bh_ctx *ctx, hipStream_t s);

@@ -63,7 +63,7 @@ SYMBOLS = ["bh_create", "bh_destroy", "tree_build", "bh_set_state", "tree_force"
            "leapfrog_step", "bh_get_state", "bh_sync", "bh_stats_get", "bh_export",
            "bh_strerror", "bh_last_error", "tree_force_vjp", "leapfrog_vjp_drift",
            "bh_state_bytes", "bh_save_state", "bh_load_state", "bh_cic_density",
-           "bh_cic_density_vjp", "tree_direct"]
+           "bh_cic_density_vjp", "tree_direct", "bh_diagnostics"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -106,6 +106,7 @@ def load():
         "bh_cic_density_vjp": ([_vp, _vp, _vp, _vp, i64, ctypes.POINTER(bh_cic_grid), _vp, _vp,
                                 _vp, _vp], c_int),
         "tree_direct": ([_vp, _vp, i64, f32, _vp, _vp, _vp], c_int),
+        "bh_diagnostics": ([_vp, ctypes.POINTER(ctypes.c_double), _vp], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -213,6 +214,17 @@ def _u8ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+DIAG_FIELDS = ("mass", "kinetic", "potential", "px", "py", "pz", "lx", "ly", "lz")
+
+
+def bh_diagnostics(ctx, stream=None) -> dict:
+    """Total mass, kinetic and potential energy, momentum and angular
+    momentum of the current state (FP64)."""
+    out = (ctypes.c_double * len(DIAG_FIELDS))()
+    _check(ctx, load().bh_diagnostics(ctx, out, _stream(stream)))
+    return dict(zip(DIAG_FIELDS, list(out)))
+
+
 def tree_direct(ctx, targets, eps, acc=None, pot=None, stream=None):
     """FP64 direct sum at caller indices `targets` (int64 CUDA tensor);
     returns (acc [nt,3], pot [nt]) as float64 CUDA tensors."""
@@ -281,6 +293,7 @@ class Tree:
                  pos_fp64: bool = False, adjoint: bool = False):
         self.ctx = bh_create(n_max, nleaf, ncrit, far_fp16, pos_fp64, adjoint)
         self.n = 0
+        self.pos_fp64 = bool(pos_fp64)
 
     def save(self):
         """Exact snapshot of the state (device bytes)."""
@@ -289,10 +302,35 @@ class Tree:
         bh_save_state(self.ctx, buf)
         return buf
 
+    def snapshot_bytes(self, n) -> int:
+        """Size of a snapshot of n particles for this context's layout."""
+        return int(n) * (32 + (24 if self.pos_fp64 else 0))
+
     def restore(self, buf, n=None):
-        bh_load_state(self.ctx, buf, self.n if n is None else n)
+        k = self.n if n is None else n
+        if buf.numel() * buf.element_size() != self.snapshot_bytes(k):
+            raise ValueError("snapshot size does not match this context and n")
+        bh_load_state(self.ctx, buf, k)
         if n is not None:
             self.n = n
+
+    def diagnostics(self) -> dict:
+        return bh_diagnostics(self.ctx)
+
+    def save_file(self, path):
+        """Write an exact snapshot of the state (restart point) to `path` (.npz)."""
+        import numpy as np
+        buf = self.save()
+        np.savez(path, state=buf.cpu().numpy(), n=np.int64(self.n))
+
+    def load_file(self, path):
+        """Restore a snapshot written by save_file (same n_max and parameters)."""
+        import numpy as np
+        import torch
+        with np.load(path, allow_pickle=False) as z:
+            n = int(z["n"])
+            buf = torch.from_numpy(z["state"]).to("cuda")
+        self.restore(buf, n)
 
     def direct(self, targets, eps):
         return tree_direct(self.ctx, targets, eps)

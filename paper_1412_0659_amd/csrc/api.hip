@@ -56,7 +56,7 @@ void free_all(bh_ctx *c) {
     f(q.P2); f(q.size);
     Groups &g = c->groups;
     f(g.flag); f(g.scan); f(g.begin); f(g.count_dev); f(g.box); f(g.npp); f(g.npc);
-    f(c->lcell); f(c->gsrc); f(c->usort); f(c->leafof); f(c->cic); f(c->inv);
+    f(c->lcell); f(c->gsrc); f(c->usort); f(c->leafof); f(c->cic); f(c->inv); f(c->diag);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
 }
@@ -198,7 +198,8 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
          dalloc(&q.P2, nc, err) && dalloc(&q.size, nc, err) && dalloc(&g.flag, n, err) &&
          dalloc(&g.scan, n, err) && dalloc(&g.begin, n + 1, err) &&
          dalloc(&g.count_dev, 1, err) && dalloc(&g.box, 2 * n, err) && dalloc(&g.npp, n, err) &&
-         dalloc(&g.npc, n, err) && dalloc(&c->cic, 65536, err) && dalloc(&c->inv, n, err);
+         dalloc(&g.npc, n, err) && dalloc(&c->cic, 65536, err) && dalloc(&c->inv, n, err) &&
+         dalloc(&c->diag, (size_t)(kDiagBlocks + 1) * kDiagN, err);
     if (ok && prm.adjoint)
         ok = dalloc(&c->lcell, 8 * 10 * nc, err) && dalloc(&c->gsrc, 8 * 4 * n, err) &&
              dalloc(&c->usort, n, err) && dalloc(&c->leafof, n, err);
@@ -276,6 +277,18 @@ int bh_get_state(bh_ctx *c, float *pos, float *vel, hipStream_t s) {
     if (!c->built) return fail(c, BH_ESTATE, "no state");
     if (pos || vel) launch_state_out(c, pos, vel, (uint32_t)c->n, s);
     BH_HIP(c, hipStreamSynchronize(s));
+    return check_status(c);
+}
+
+int bh_diagnostics(bh_ctx *c, double *out, hipStream_t s) {
+    if (!c || !out) return BH_EINVAL;
+    if (!c->built) return fail(c, BH_ESTATE, "no state");
+    launch_diagnostics(c, s);
+    BH_HIP(c, hipGetLastError());
+    BH_HIP(c, hipMemcpyAsync(out, c->diag + (size_t)kDiagBlocks * kDiagN, kDiagN * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+    BH_HIP(c, hipStreamSynchronize(s));
+    if (!c->have_acc) out[2] = std::nan("");
     return check_status(c);
 }
 

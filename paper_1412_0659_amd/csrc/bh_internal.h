@@ -20,6 +20,8 @@ constexpr int kGrid = 1024;             // fixed grid of the level-wise build ke
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr int kStackMax = 1408;         // walk stack bound: 21 levels x 64 ranges + root
+constexpr int kDiagN = 9;               // diagnostics: M, KE, PE, p xyz, L xyz
+constexpr int kDiagBlocks = 1024;       // blocks of the diagnostics reduction
 
 // device status word bits
 constexpr uint32_t kStNonFinite = 1u;
@@ -98,6 +100,7 @@ struct bh_ctx {
     uint32_t *leafof = nullptr;  // [n] leaf cell of each sorted particle
     double *cic = nullptr;       // [65536] accumulator of the surface-density grid
     uint32_t *inv = nullptr;     // [n] sorted slot of each caller index (direct sum)
+    double *diag = nullptr;      // [kDiagBlocks + 1][kDiagN] diagnostics partials, result
 
     bool built = false, have_acc = false;
     float acc_theta = 0.f, acc_eps = 0.f;
@@ -165,6 +168,7 @@ void launch_unsort(bh_ctx *c, float *acc, float *pot, uint32_t n, hipStream_t st
 void launch_state_out(bh_ctx *c, float *pos, float *vel, uint32_t n, hipStream_t st);
 void launch_totals(bh_ctx *c, uint32_t n, hipStream_t st);
 void launch_count_leaves(bh_ctx *c, hipStream_t st);
+void launch_diagnostics(bh_ctx *c, hipStream_t st);  // result at diag + kDiagBlocks * kDiagN
 void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }

@@ -152,6 +152,66 @@ void launch_state_out(bh_ctx *c, float *pos, float *vel, uint32_t n, hipStream_t
                        vel);
 }
 
+// Conserved quantities of the state, FP64: total mass, kinetic energy,
+// potential energy 1/2 sum m phi (phi of the last force evaluation, which
+// excludes the self pair), momentum and angular momentum about the origin
+// (positions as held: the FP64 master copy when kept).  Each block writes
+// its partial sums; one wave folds them in block order, so the result does
+// not depend on scheduling.
+__global__ __launch_bounds__(256) void k_diag_partial(State s, const float4 *__restrict__ acc,
+                                                      uint32_t n, double *part) {
+    double v[kDiagN];
+#pragma unroll
+    for (int k = 0; k < kDiagN; ++k) v[k] = 0.0;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        const double m = s.m[i];
+        const double x = s.x64 ? s.x64[i] : (double)s.x[i];
+        const double y = s.x64 ? s.y64[i] : (double)s.y[i];
+        const double z = s.x64 ? s.z64[i] : (double)s.z[i];
+        const double vx = s.vx[i], vy = s.vy[i], vz = s.vz[i];
+        v[0] += m;
+        v[1] += 0.5 * m * (vx * vx + vy * vy + vz * vz);
+        v[2] += 0.5 * m * (double)acc[i].w;
+        v[3] += m * vx;
+        v[4] += m * vy;
+        v[5] += m * vz;
+        v[6] += m * (y * vz - z * vy);
+        v[7] += m * (z * vx - x * vz);
+        v[8] += m * (x * vy - y * vx);
+    }
+    __shared__ double lds[4][kDiagN];
+#pragma unroll
+    for (int k = 0; k < kDiagN; ++k) {
+        double t = v[k];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) t += __shfl_xor(t, d, 64);
+        if (lane_id() == 0) lds[threadIdx.x >> 6][k] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kDiagN)
+        part[(size_t)blockIdx.x * kDiagN + threadIdx.x] =
+            ((lds[0][threadIdx.x] + lds[1][threadIdx.x]) + lds[2][threadIdx.x]) + lds[3][threadIdx.x];
+}
+
+__global__ void k_diag_final(const double *__restrict__ part, uint32_t nb, double *out) {
+    const uint32_t k = threadIdx.x;
+    if (k >= (uint32_t)kDiagN) return;
+    double t = 0.0;
+    for (uint32_t b = 0; b < nb; ++b) t += part[(size_t)b * kDiagN + k];
+    out[k] = t;
+}
+
+void launch_diagnostics(bh_ctx *c, hipStream_t st) {
+    const uint32_t n = (uint32_t)c->n;
+    uint32_t nb = cdiv(n, 256);
+    if (nb > (uint32_t)kDiagBlocks) nb = kDiagBlocks;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_diag_partial, dim3(nb), dim3(256), 0, st, c->st[c->cur],
+                       (const float4 *)c->acc, n, c->diag);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, (const double *)c->diag, nb,
+                       c->diag + (size_t)kDiagBlocks * kDiagN);
+}
+
 // sum over groups of npp * size and npc * size (integers: order-free)
 __global__ __launch_bounds__(256) void k_totals(const uint32_t *__restrict__ gbeg,
                                                 const uint32_t *__restrict__ ngroups,
