@@ -11,17 +11,21 @@
 //               dM/dm_k = 1, dcom/dm_k = s / M, dQ/dm_k = s s^T (the centre of
 //               mass dependence of Q cancels because sum m s = 0).
 // The walk (walk_common.h) is repeated exactly, so the lists are those of the
-// force evaluation.  For each staged chunk of sources, pass A (lane = target,
-// slice) accumulates the target terms in registers; pass B (lane = source)
-// loops over the group's targets and adds the source terms to FP64
-// accumulators with one atomic per source and group.  The self pair (zero
-// separation by construction) contributes nothing.
+// force evaluation.  Particle-cell chunks: lane = cell, looping over the
+// group's targets; each pair's J^T u is added to the cell's adjoint and, summed
+// over the lanes with DPP, subtracted from the target's.  Particle-particle
+// chunks: pass A (lane = target, slice) accumulates the target terms in
+// registers, pass B (lane = source) loops over the targets for the source
+// terms.  Source terms reach FP64 accumulators with one atomic per source
+// and group.  The self pair (zero separation by construction) contributes
+// nothing.
 //
-// The accumulators come in kXcd copies, one per XCD: a wave adds into the
-// copy of the XCD it runs on (read from the hardware XCC id), with atomics
-// of workgroup scope, which that XCD's L2 executes; device-scope atomics
-// would all travel to the memory side.  Every writer of a copy shares one
-// L2, so the copy is exact; the copies are summed after the walk.
+// The accumulators are field-major (cell adjoint q of cell c at q * cap + c),
+// so the lanes of one atomic instruction, neighbouring cells or the
+// particles of one leaf, share a few cache lines; and they come in kXcd
+// copies, one per XCD: a wave adds into the copy of the XCD it runs on (read
+// from the hardware XCC id), so no cache line is updated from two XCDs.  The
+// copies are summed after the walk.
 #include "walk_common.h"
 
 namespace bh {
@@ -139,7 +143,7 @@ __device__ __forceinline__ float wave_total(float v) {
 }
 
 struct VjpLds {
-    float4 stage[3][kChunk + 1];  // source records + the null source
+    float4 stage[1][kChunk + 1];  // particle sources of one chunk + the null source
     uint32_t sidx[kChunk + 1];    // particle index of staged particle sources
     float4 tp[64], tu[64];        // the group's targets: position + mass, cotangent
     uint32_t tidx[64];
@@ -153,7 +157,8 @@ struct VPhase {
     float gx, gy, gz;
 };
 
-template <bool kIsPc, bool kEps0>
+// Target terms of one staged chunk of particle sources for one phase.
+template <bool kEps0>
 __device__ __forceinline__ void vjp_targets(VPhase &ph, uint32_t n, const VjpLds &L, float eps2) {
     const uint32_t r = ph.r;
     const uint32_t rounds = (n + r - 1u) / r;
@@ -161,13 +166,8 @@ __device__ __forceinline__ void vjp_targets(VPhase &ph, uint32_t n, const VjpLds
     for (uint32_t j = 0; j < rounds; ++j, k += r) {
         const uint32_t kk = k < n ? k : (uint32_t)kNull;
         float wx, wy, wz, gm;
-        if (kIsPc) {
-            pc_adj<false>(ph.tgt, ph.u, L.stage[0][kk], L.stage[1][kk], L.stage[2][kk], eps2, wx,
-                          wy, wz, gm, nullptr);
-        } else {
-            pp_adj<kEps0>(ph.tgt, ph.u, L.stage[0][kk], eps2, wx, wy, wz, gm);
-            if (L.sidx[kk] == ph.tidx) wx = wy = wz = 0.f;
-        }
+        pp_adj<kEps0>(ph.tgt, ph.u, L.stage[0][kk], eps2, wx, wy, wz, gm);
+        if (L.sidx[kk] == ph.tidx) wx = wy = wz = 0.f;
         ph.gx -= wx;
         ph.gy -= wy;
         ph.gz -= wz;
@@ -195,8 +195,6 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
     L.tidx[lane] = own ? ti : kNone;
     if (lane == 0) {
         L.stage[0][kNull] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
-        L.stage[1][kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
-        L.stage[2][kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
         L.sidx[kNull] = kNone;
     }
 
@@ -270,8 +268,8 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
             L.stage[0][lane] = P;
             L.sidx[lane] = valid ? j : kNone;
             __syncthreads();
-            vjp_targets<false, kEps0>(p1, m, L, a.eps2);
-            if (two) vjp_targets<false, kEps0>(p2, m, L, a.eps2);
+            vjp_targets<kEps0>(p1, m, L, a.eps2);
+            if (two) vjp_targets<kEps0>(p2, m, L, a.eps2);
             float sx = 0.f, sy = 0.f, sz = 0.f, sm = 0.f;
             for (uint32_t t = 0; t < gn; ++t) {
                 float wx, wy, wz, gm;
