@@ -73,7 +73,11 @@ typedef struct bh_params {
     int32_t adjoint;  /* 1: allocate the buffers of tree_force_vjp: FP64 cell and
                          particle adjoints, one copy per XCD (8): 640 bytes per
                          cell of capacity + 276 bytes per particle */
-    int32_t reserved[3];
+    int32_t curve;    /* space-filling curve of the keys: 0 Morton, 1 Peano-Hilbert
+                         (the paper's, Sec. III.B.1).  Every octree cell is one key
+                         range under both, so the cells are the same; only their
+                         order and the particle order inside them differ. */
+    int32_t reserved[2];
 } bh_params;
 
 typedef struct bh_ctx bh_ctx;

@@ -215,6 +215,112 @@ void orc_group_boxes(int64_t ng, const int64_t *gbeg, const int64_t *gcnt, const
 
 /* Integer corner coordinates of a cell: the 3*level bits of the prefix,
  * de-interleaved per axis (x the high bit of each digit). */
+/* Peano-Hilbert curve, following J. Skilling, "Programming the Hilbert
+ * curve", AIP Conf. Proc. 707, 381 (2004): integer coordinates of b bits
+ * per axis <-> the curve's "transposed" index, whose bits interleaved like a
+ * Morton key (X[0] the high bit of each 3-bit digit) give the position along
+ * the curve.  The top 3l bits of a b-bit index are the l-bit index of the
+ * coordinates' top l bits, so every octree cell is one contiguous key range,
+ * as under the Morton order. */
+static void ph_from_axes(uint32_t X[3], int b) {
+    if (b < 1) return;
+    const uint32_t top = 1u << (b - 1);
+    for (uint32_t Q = top; Q > 1; Q >>= 1) {
+        const uint32_t P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) {
+                X[0] ^= P;                       /* invert the lower bits of X[0] */
+            } else {
+                uint32_t t = (X[0] ^ X[i]) & P;  /* swap the lower bits of X[0], X[i] */
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];                                /* Gray encode */
+    X[2] ^= X[1];
+    uint32_t t = 0;
+    for (uint32_t Q = top; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+}
+
+static void ph_to_axes(uint32_t X[3], int b) {
+    if (b < 1) return;
+    const uint32_t end = 2u << (b - 1);
+    uint32_t t = X[2] >> 1;                      /* Gray decode */
+    X[2] ^= X[1];
+    X[1] ^= X[0];
+    X[0] ^= t;
+    for (uint32_t Q = 2; Q != end; Q <<= 1) {
+        const uint32_t P = Q - 1;
+        for (int i = 2; i >= 0; --i) {
+            if (X[i] & Q) {
+                X[0] ^= P;
+            } else {
+                uint32_t u = (X[0] ^ X[i]) & P;
+                X[0] ^= u;
+                X[i] ^= u;
+            }
+        }
+    }
+}
+
+static uint64_t interleave3(const uint32_t X[3], int b) {
+    uint64_t k = 0;
+    for (int i = b - 1; i >= 0; --i)
+        k = (k << 3) | ((uint64_t)((X[0] >> i) & 1u) << 2) | ((uint64_t)((X[1] >> i) & 1u) << 1) |
+            (uint64_t)((X[2] >> i) & 1u);
+    return k;
+}
+
+static void deinterleave3(uint64_t k, int b, uint32_t X[3]) {
+    X[0] = X[1] = X[2] = 0;
+    for (int i = b - 1; i >= 0; --i) {
+        uint32_t d = (uint32_t)(k >> (3 * i)) & 7u;
+        X[0] = (X[0] << 1) | (d >> 2);
+        X[1] = (X[1] << 1) | ((d >> 1) & 1u);
+        X[2] = (X[2] << 1) | (d & 1u);
+    }
+}
+
+/* Peano-Hilbert index of n integer points q[n][3] with b bits per axis, and
+ * the inverse (index -> coordinates). */
+void orc_ph_index(int64_t n, const uint32_t *q, int b, uint64_t *keys) {
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t X[3] = {q[3 * i], q[3 * i + 1], q[3 * i + 2]};
+        ph_from_axes(X, b);
+        keys[i] = interleave3(X, b);
+    }
+}
+
+void orc_ph_coords(int64_t n, const uint64_t *keys, int b, uint32_t *q) {
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t X[3];
+        deinterleave3(keys[i], b, X);
+        ph_to_axes(X, b);
+        q[3 * i] = X[0];
+        q[3 * i + 1] = X[1];
+        q[3 * i + 2] = X[2];
+    }
+}
+
+/* 63-bit Peano-Hilbert keys of FP32 positions, with the Morton key's
+ * quantisation. */
+void orc_keys_ph(int64_t n, const float *pos, const float *lo, float scale, uint64_t *keys) {
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t X[3];
+        for (int a = 0; a < 3; ++a) {
+            float t = pos[3 * i + a] - lo[a];
+            float u = t * scale;
+            uint32_t v = (uint32_t)u;
+            X[a] = v > KEY_MAXQ ? KEY_MAXQ : v;
+        }
+        ph_from_axes(X, KEY_BITS);
+        keys[i] = interleave3(X, KEY_BITS);
+    }
+}
+
 static void cell_coords(uint64_t prefix, int lev, uint64_t p[3]) {
     p[0] = p[1] = p[2] = 0;
     for (int b = lev - 1; b >= 0; --b) {
@@ -230,13 +336,14 @@ static void cell_coords(uint64_t prefix, int lev, uint64_t p[3]) {
  * the second moment about the centre of mass, not trace-free).  Parent:
  * M = sum M_c, S = sum S_c, com = S / M,
  * Q = sum (Q_c + M_c d d^T) with d = com_c - com (parallel axis).
- * Geometry: cell size l = side * 2^-level, centre = lo + (p + 1/2) l, and
- * delta = |com - centre|.  Q is stored xx, yy, zz, xy, xz, yz.
+ * Geometry: cell size l = side * 2^-level, centre = lo + (p + 1/2) l with p
+ * the cell's octant decoded from its key prefix (Morton, or Peano-Hilbert
+ * when curve = 1), and delta = |com - centre|.  Q is stored xx, yy, zz, xy, xz, yz.
  * Also writes the FP32 copies the opening test uses: comf, lf, deltaf. */
 void orc_moments(int64_t ncell, const int32_t *level, const uint64_t *prefix,
                  const int64_t *begin, const int64_t *count, const int64_t *child0,
                  const int32_t *nchild, const float *x, const float *y, const float *z,
-                 const float *m, const float *lo, float side, double *M, double *S,
+                 const float *m, const float *lo, float side, int curve, double *M, double *S,
                  double *com, double *Q, float *comf, float *lf, float *deltaf) {
     for (int64_t c = ncell - 1; c >= 0; --c) {
         double mm = 0.0, s[3] = {0.0, 0.0, 0.0}, q[6] = {0, 0, 0, 0, 0, 0};
@@ -287,7 +394,14 @@ void orc_moments(int64_t ncell, const int32_t *level, const uint64_t *prefix,
         for (int k = 0; k < 6; ++k) Q[6 * c + k] = q[k];
 
         uint64_t p[3];
-        cell_coords(prefix[c], level[c], p);
+        if (curve == 1) {  /* the cell's octant from its Peano-Hilbert prefix */
+            uint32_t X[3];
+            deinterleave3(prefix[c], level[c], X);
+            ph_to_axes(X, level[c]);
+            p[0] = X[0]; p[1] = X[1]; p[2] = X[2];
+        } else {
+            cell_coords(prefix[c], level[c], p);
+        }
         double lc = (double)side * ldexp(1.0, -level[c]);
         double e0 = cm[0] - ((double)lo[0] + ((double)p[0] + 0.5) * lc);
         double e1 = cm[1] - ((double)lo[1] + ((double)p[1] + 0.5) * lc);

@@ -64,8 +64,12 @@ def lib():
         L.orc_groups.restype = _i64
         L.orc_group_boxes.argtypes = [_i64, _i64p, _i64p, _f32p, _f32p, _f32p, _f32p, _f32p]
         L.orc_moments.argtypes = [_i64, _i32p, _u64p, _i64p, _i64p, _i64p, _i32p, _f32p, _f32p,
-                                  _f32p, _f32p, _f32p, ctypes.c_float, _f64p, _f64p, _f64p,
+                                  _f32p, _f32p, _f32p, ctypes.c_float, _int, _f64p, _f64p, _f64p,
                                   _f64p, _f32p, _f32p, _f32p]
+        _u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        L.orc_ph_index.argtypes = [_i64, _u32p, _int, _u64p]
+        L.orc_ph_coords.argtypes = [_i64, _u64p, _int, _u32p]
+        L.orc_keys_ph.argtypes = [_i64, _f32p, _f32p, ctypes.c_float, _u64p]
         L.orc_open_radius.argtypes = [_i64, _f32p, _f32p, ctypes.c_float, _f32p]
         L.orc_walk.argtypes = [_i64, _i64p, _i64p, _i64p, _f32p, _f32p, _i64, _i64p, _i64p,
                                _i64p, _i32p, _f64p, _f64p, _f64p, _f32p, _f32p, _f32p, _f32p,
@@ -105,6 +109,30 @@ def morton_keys(pos, lo, scale):
     pos = _f32(pos).reshape(-1, 3)
     out = np.empty(pos.shape[0], np.uint64)
     lib().orc_keys(pos.shape[0], pos, _f32(lo), ctypes.c_float(scale), out)
+    return out
+
+
+def ph_keys(pos, lo, scale):
+    """63-bit Peano-Hilbert keys with the Morton key's quantisation."""
+    pos = _f32(pos).reshape(-1, 3)
+    out = np.empty(pos.shape[0], np.uint64)
+    lib().orc_keys_ph(pos.shape[0], pos, _f32(lo), ctypes.c_float(scale), out)
+    return out
+
+
+def ph_index(q, bits):
+    """Peano-Hilbert index of integer points q [n, 3] with `bits` per axis."""
+    q = np.ascontiguousarray(q, dtype=np.uint32).reshape(-1, 3)
+    out = np.empty(q.shape[0], np.uint64)
+    lib().orc_ph_index(q.shape[0], q, int(bits), out)
+    return out
+
+
+def ph_coords(keys, bits):
+    """Inverse of ph_index."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    out = np.empty((keys.shape[0], 3), np.uint32)
+    lib().orc_ph_coords(keys.shape[0], keys, int(bits), out)
     return out
 
 
@@ -164,7 +192,7 @@ def group_boxes(gbeg, gcnt, x, y, z):
 
 # --- O6 --------------------------------------------------------------------------
 
-def moments(cells, x, y, z, m, lo, side):
+def moments(cells, x, y, z, m, lo, side, curve="morton"):
     nc = cells["ncell"]
     M = np.empty(nc)
     S = np.empty(3 * nc)
@@ -175,7 +203,8 @@ def moments(cells, x, y, z, m, lo, side):
     deltaf = np.empty(nc, np.float32)
     lib().orc_moments(nc, cells["level"], cells["prefix"], cells["begin"], cells["count"],
                       cells["child0"], cells["nchild"], _f32(x), _f32(y), _f32(z), _f32(m),
-                      _f32(lo), ctypes.c_float(side), M, S, com, Q, comf, lf, deltaf)
+                      _f32(lo), ctypes.c_float(side), 1 if curve == "ph" else 0, M, S, com, Q,
+                      comf, lf, deltaf)
     return dict(M=M, S=S.reshape(nc, 3), com=com.reshape(nc, 3), Q=Q.reshape(nc, 6),
                 comf=comf.reshape(nc, 3), lf=lf, deltaf=deltaf)
 
@@ -219,12 +248,14 @@ class Tree:
         return np.cumsum(g)
 
 
-def build_tree(pos, mass, nleaf: int = NLEAF, ncrit: int = NCRIT) -> Tree:
+def build_tree(pos, mass, nleaf: int = NLEAF, ncrit: int = NCRIT, curve: str = "morton") -> Tree:
+    """The whole tree of Sec. III.B.1 / Sec. I.A; curve "morton" or "ph"
+    (Peano-Hilbert, the paper's curve): the same cells in another order."""
     pos = _f32(pos).reshape(-1, 3)
     mass = _f32(mass).reshape(-1)
     n = pos.shape[0]
     lo, side, scale = bbox(pos)
-    keys = morton_keys(pos, lo, scale)
+    keys = ph_keys(pos, lo, scale) if curve == "ph" else morton_keys(pos, lo, scale)
     perm = sort_keys(keys)
     skeys = keys[perm]
     sp = pos[perm]
@@ -233,7 +264,7 @@ def build_tree(pos, mass, nleaf: int = NLEAF, ncrit: int = NCRIT) -> Tree:
     cells = build_cells(skeys, nleaf)
     gbeg, gcnt, gcell = make_groups(cells, ncrit)
     gc, gh = group_boxes(gbeg, gcnt, x, y, z)
-    mom = moments(cells, x, y, z, m, lo, side)
+    mom = moments(cells, x, y, z, m, lo, side, curve)
     return Tree(n, lo, side, scale, keys, perm, skeys, x, y, z, m, cells, gbeg, gcnt, gcell,
                 gc, gh, mom)
 

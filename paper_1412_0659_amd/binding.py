@@ -43,7 +43,8 @@ class BhError(RuntimeError):
 class bh_params(ctypes.Structure):
     _fields_ = [("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32),
                 ("far_fp16", ctypes.c_int32), ("pos_fp64", ctypes.c_int32),
-                ("adjoint", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("adjoint", ctypes.c_int32), ("curve", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class bh_cic_grid(ctypes.Structure):
@@ -143,9 +144,13 @@ def _stream(stream=None):
 
 # --- the C entry points, same names ------------------------------------------
 
+CURVES = {"morton": 0, "ph": 1}
+
+
 def bh_create(n_max: int, nleaf: int = 16, ncrit: int = 64, far_fp16: bool = False,
-              pos_fp64: bool = False, adjoint: bool = False):
-    p = bh_params(nleaf, ncrit, int(bool(far_fp16)), int(bool(pos_fp64)), int(bool(adjoint)))
+              pos_fp64: bool = False, adjoint: bool = False, curve: str = "morton"):
+    p = bh_params(nleaf, ncrit, int(bool(far_fp16)), int(bool(pos_fp64)), int(bool(adjoint)),
+                  CURVES[curve])
     out = _vp()
     rc = load().bh_create(ctypes.byref(out), int(n_max), ctypes.byref(p))
     _check(None, rc)
@@ -290,8 +295,8 @@ class Tree:
     """Owns one library context; methods call the C entry points."""
 
     def __init__(self, n_max: int, nleaf: int = 16, ncrit: int = 64, far_fp16: bool = False,
-                 pos_fp64: bool = False, adjoint: bool = False):
-        self.ctx = bh_create(n_max, nleaf, ncrit, far_fp16, pos_fp64, adjoint)
+                 pos_fp64: bool = False, adjoint: bool = False, curve: str = "morton"):
+        self.ctx = bh_create(n_max, nleaf, ncrit, far_fp16, pos_fp64, adjoint, curve)
         self.n = 0
         self.pos_fp64 = bool(pos_fp64)
 

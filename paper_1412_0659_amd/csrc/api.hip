@@ -137,7 +137,7 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
     if (p) prm = *p;
     if (n_max <= 0 || prm.nleaf < 1 || prm.nleaf > 64 || prm.ncrit < 1 || prm.ncrit > 64 ||
         prm.far_fp16 < 0 || prm.far_fp16 > 1 || prm.pos_fp64 < 0 || prm.pos_fp64 > 1 ||
-        prm.adjoint < 0 || prm.adjoint > 1)
+        prm.adjoint < 0 || prm.adjoint > 1 || prm.curve < 0 || prm.curve > 1)
         return BH_EINVAL;
     // cells: <= n leaves + 21 levels x n / (nleaf + 1) internal cells; the walk
     // packs a cell index into 29 bits

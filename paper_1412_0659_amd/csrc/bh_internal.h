@@ -173,4 +173,53 @@ void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
+// Peano-Hilbert curve (the curve of Sec. III.B.1), after J. Skilling,
+// "Programming the Hilbert curve", AIP Conf. Proc. 707, 381 (2004): integer
+// coordinates of b bits per axis are turned in place into the curve's
+// transposed index, whose bits interleaved like a Morton key (X[0] the high
+// bit of each digit) are the position along the curve; ph_decode inverts it.
+// The top 3l bits of a key are the l-bit key of the coordinates' top l bits,
+// so each octree cell is one key range, as with Morton keys.
+__device__ __forceinline__ void ph_encode(uint32_t X[3], int b) {
+    if (b < 1) return;
+    const uint32_t top = 1u << (b - 1);
+    for (uint32_t Q = top; Q > 1u; Q >>= 1) {
+        const uint32_t P = Q - 1u;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const uint32_t sw = (X[0] ^ X[i]) & P;
+            const bool inv = (X[i] & Q) != 0u;
+            X[0] ^= inv ? P : sw;      // invert the low bits of X[0], or swap them
+            if (!inv) X[i] ^= sw;      //   with those of X[i]
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t t = 0;
+    for (uint32_t Q = top; Q > 1u; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1u;
+    X[0] ^= t;
+    X[1] ^= t;
+    X[2] ^= t;
+}
+
+__device__ __forceinline__ void ph_decode(uint32_t X[3], int b) {
+    if (b < 1) return;
+    const uint32_t end = 2u << (b - 1);
+    const uint32_t t = X[2] >> 1;
+    X[2] ^= X[1];
+    X[1] ^= X[0];
+    X[0] ^= t;
+    for (uint32_t Q = 2; Q != end; Q <<= 1) {
+        const uint32_t P = Q - 1u;
+#pragma unroll
+        for (int i = 2; i >= 0; --i) {
+            const uint32_t sw = (X[0] ^ X[i]) & P;
+            const bool inv = (X[i] & Q) != 0u;
+            X[0] ^= inv ? P : sw;
+            if (!inv) X[i] ^= sw;
+        }
+    }
+}
+
 }  // namespace bh

@@ -100,6 +100,9 @@ __device__ __forceinline__ uint32_t quantise(float v, float lo, float scale) {
     return q > 0x1fffffu ? 0x1fffffu : q;
 }
 
+// 63-bit keys: the quantised coordinates interleaved (Morton), or their
+// Peano-Hilbert transposed index interleaved the same way
+template <bool kPH>
 __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ x,
                                               const float *__restrict__ y,
                                               const float *__restrict__ z, uint32_t n,
@@ -109,15 +112,20 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ x,
     uint32_t i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     float lo0 = box[0], lo1 = box[1], lo2 = box[2], scale = box[4];
-    uint64_t k = (spread3(quantise(x[i], lo0, scale)) << 2) |
-                 (spread3(quantise(y[i], lo1, scale)) << 1) | spread3(quantise(z[i], lo2, scale));
-    key[i] = k;
+    uint32_t X[3] = {quantise(x[i], lo0, scale), quantise(y[i], lo1, scale),
+                     quantise(z[i], lo2, scale)};
+    if (kPH) ph_encode(X, kKeyBits);
+    key[i] = (spread3(X[0]) << 2) | (spread3(X[1]) << 1) | spread3(X[2]);
     idx[i] = i;
 }
 
 void launch_keys(bh_ctx *c, const State &s, uint32_t n, hipStream_t st) {
-    hipLaunchKernelGGL(k_keys, dim3(cdiv(n, 256)), dim3(256), 0, st, s.x, s.y, s.z, n,
-                       (const float *)c->box, c->sort.key[0], c->sort.idx[0]);
+    if (c->p.curve == 1)
+        hipLaunchKernelGGL(k_keys<true>, dim3(cdiv(n, 256)), dim3(256), 0, st, s.x, s.y, s.z, n,
+                           (const float *)c->box, c->sort.key[0], c->sort.idx[0]);
+    else
+        hipLaunchKernelGGL(k_keys<false>, dim3(cdiv(n, 256)), dim3(256), 0, st, s.x, s.y, s.z,
+                           n, (const float *)c->box, c->sort.key[0], c->sort.idx[0]);
 }
 
 // ---- LSD radix sort, 8 bits per pass -------------------------------------

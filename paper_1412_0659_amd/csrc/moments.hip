@@ -102,13 +102,15 @@ __device__ __forceinline__ void cell_coords(uint64_t prefix, uint32_t lev, uint3
     p[0] = a; p[1] = b; p[2] = d;
 }
 
-__global__ __launch_bounds__(256) void k_moments_final(Cells c, const float *__restrict__ box) {
+__global__ __launch_bounds__(256) void k_moments_final(Cells c, const float *__restrict__ box,
+                                                       int curve) {
     uint32_t nc = c.ls[kLevels];
     double lo0 = box[0], lo1 = box[1], lo2 = box[2], side = box[3];
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) {
         uint32_t lev = c.level[i];
         uint32_t p[3];
-        cell_coords(c.prefix[i], lev, p);
+        cell_coords(c.prefix[i], lev, p);     // the digits, deinterleaved
+        if (curve == 1) ph_decode(p, (int)lev);  // Peano-Hilbert prefix -> octant
         double lc = side * (1.0 / (double)(1u << lev));
         double c0 = c.com[3 * i], c1 = c.com[3 * i + 1], c2 = c.com[3 * i + 2];
         double e0 = c0 - (lo0 + ((double)p[0] + 0.5) * lc);
@@ -138,7 +140,7 @@ void launch_moments(bh_ctx *ctx, hipStream_t st) {
     for (int l = kLevels - 2; l >= 0; --l)
         hipLaunchKernelGGL(k_moments_up, dim3(kGrid), dim3(256), 0, st, c, l);
     hipLaunchKernelGGL(k_moments_final, dim3(kGrid * 2), dim3(256), 0, st, c,
-                       (const float *)ctx->box);
+                       (const float *)ctx->box, (int)ctx->p.curve);
 }
 
 // r_open^2 = (fl32(l / theta) + delta)^2 in FP32, stored in wA.w

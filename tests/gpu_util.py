@@ -14,9 +14,9 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device())
 
 
-def gpu_tree(pos, mass, nleaf=16, ncrit=64, vel=None, far_fp16=False):
+def gpu_tree(pos, mass, nleaf=16, ncrit=64, vel=None, far_fp16=False, curve="morton"):
     from paper_1412_0659_amd import Tree
-    t = Tree(max(1, len(mass)), nleaf, ncrit, far_fp16)
+    t = Tree(max(1, len(mass)), nleaf, ncrit, far_fp16, curve=curve)
     if vel is None:
         t.build(to_dev(pos), to_dev(mass))
     else:
