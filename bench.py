@@ -263,6 +263,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="disk_halo_13m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--curve", choices=("morton", "ph"), default="morton",
+                    help="space-filling curve of the keys (the same cells either way)")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--precision-sweep", action="store_true",
@@ -320,7 +322,7 @@ def main(argv=None):
     pos = torch.from_numpy(snap.pos).to(dev)
     vel = torch.from_numpy(snap.vel).to(dev)
     mass = torch.from_numpy(snap.mass).to(dev)
-    tree = bh.Tree(snap.n)
+    tree = bh.Tree(snap.n, curve=args.curve)
     tree.set_state(pos, vel, mass)
     tree.sync()
     for k in range(args.warmup):
@@ -359,7 +361,7 @@ def main(argv=None):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": snap.n, "theta": theta, "eps": eps, "dt": dt,
-                   "nleaf": 16, "ncrit": 64, "model": "exponential disk + Hernquist halo"
+                   "nleaf": 16, "ncrit": 64, "curve": args.curve, "model": "exponential disk + Hernquist halo"
                    if w["model"] == "disk_halo" else "Plummer sphere"},
         "tflops_step": flops / wall / 1e12,
         "tflops_walk": walk_tflops,
