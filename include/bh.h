@@ -256,7 +256,17 @@ typedef enum bh_array {
                                (written by the walk) */
     BH_ARR_GROUP_NPP = 20,  /* u32 [ngroups] particle-particle sources of the last walk */
     BH_ARR_GROUP_NPC = 21,  /* u32 [ngroups] particle-cell sources of the last walk */
-    BH_ARR_ACC_SORTED = 22  /* f32 [n][4] ax, ay, az, potential in sorted order */
+    BH_ARR_ACC_SORTED = 22, /* f32 [n][4] ax, ay, az, potential in sorted order */
+    BH_ARR_BOUNDARY_FLAG = 23,  /* u32 [ncells] bit 0: in the boundary tree,
+                                   bit 1: terminal (after bh_boundary) */
+    BH_ARR_BOUNDARY_CELLS = 24, /* u32 [nterm] terminal boundary cells, cell order */
+    BH_ARR_BOUNDARY_BOX = 25,   /* f32 [nterm][8] centre xyz, 0, widened half size
+                                   xyz, 0 of each terminal cell */
+    BH_ARR_LET_ORIGIN = 26,     /* u32 [let cells][2] (source index, source cell);
+                                   0xffffffff for virtual cells (after bh_let_build) */
+    BH_ARR_LET_NODE = 27,       /* u32 [let cells][2] internal: (first child, count);
+                                   leaf: (first particle, count | 0x80000000) */
+    BH_ARR_LET_COMF = 28        /* f32 [let cells][4] centre of mass, r_open^2 */
 } bh_array;
 
 /* Copy one array of the last build / walk to host memory `dst` (capacity
@@ -265,6 +275,96 @@ typedef enum bh_array {
  * BH_ESTATE (nothing built). */
 int bh_export(bh_ctx *ctx, int array, void *dst, int64_t cap_bytes, int64_t *nbytes,
               hipStream_t s);
+
+/* ---- Several spatial domains on one device (Sec. III.B) -------------------
+ *
+ * The paper splits the particles into one domain per GPU along the
+ * space-filling curve (Sec. III.B.1), keys every domain in one global box so
+ * each local tree is a branch of one global octree, and gives each domain
+ * the remote cells and particles its targets need as local essential trees
+ * (LETs, Sec. III.B.2).  These calls run those steps with every domain a
+ * context on the same device: the forces a domain receives are its own tree
+ * walk plus the walk of the remote trees, and they agree with one walk of a
+ * single tree over all particles within the opening-angle error. */
+
+/* Key every later build of ctx in the cube [lo, lo + side)^3 (host lo[3])
+ * instead of the particles' own bounding box (Sec. III.B.1: the global
+ * bounding box all domains share).  lo == NULL restores the own box.  A
+ * particle outside the cube (x < lo or fl32(x - lo) > side on some axis)
+ * latches a device status reported as BH_EINVAL by the next synchronising
+ * call.  Errors: BH_EINVAL (lo not finite,
+ * side <= 0 or not finite). */
+int bh_set_box(bh_ctx *ctx, const float *lo, float side);
+
+/* Cut the sorted particles of ctx into p domains along the curve
+ * (Sec. III.B.1: cuts that balance the tree-walk operations, no domain more
+ * than a cap above the average particle count).  Needs a force walk of the
+ * current tree.  Cost of a particle: 23 npp + 65 npc of its group's last
+ * walk (the operation counts of Sec. V.A).  Cut j (host int64 cuts[p + 1],
+ * cuts[0] = 0, cuts[p] = n) is the first sorted slot i at which the running
+ * cost of slots [0, i) reaches j/p of the total, clamped so that no domain
+ * holds more than C = floor(cap n / p) particles: cuts[j] in
+ * [max(cuts[j-1], n - (p - j) C), min(cuts[j-1] + C, n)].  Domains may be
+ * empty.  Synchronises s.  Errors: BH_EINVAL (p outside [1, n], cap < 1 or
+ * C p < n), BH_ESTATE (no walk since the last build). */
+int bh_decompose(bh_ctx *ctx, int32_t p, float cap, int64_t *cuts, hipStream_t s);
+
+/* Copy the particles in sorted slots [lo, hi) to device arrays in sorted
+ * order: pos [hi - lo][3], vel [hi - lo][3], mass [hi - lo] and ids
+ * [hi - lo] (the caller index of each); any output may be NULL.  This is
+ * the particle exchange of Sec. III.B.1 for one domain.  Errors: BH_EINVAL
+ * (not 0 <= lo <= hi <= n), BH_ESTATE (nothing built). */
+int bh_domain_extract(bh_ctx *ctx, int64_t lo, int64_t hi, float *pos, float *vel,
+                      float *mass, uint32_t *ids, hipStream_t s);
+
+/* Forces on ctx's particles from every cell and particle of another
+ * context's tree (the remote tree walked in full, Sec. III.B.2), added to
+ * the caller-order device outputs acc [n][3] and pot [n] (either may be
+ * NULL).  Prepares src's opening radii for theta; overwrites ctx's sorted
+ * accelerations, so a later leapfrog_step recomputes the own forces.
+ * Errors: BH_EINVAL (src == ctx, theta, eps, different devices), BH_ESTATE
+ * (either tree not built). */
+int tree_force_add(bh_ctx *ctx, bh_ctx *src, float theta, float eps, float *acc, float *pot,
+                   hipStream_t s);
+
+/* Boundary tree of ctx's tree (Sec. III.B.2, the cells on the edge of the
+ * local particle set and their parents): from the root through cells of
+ * more than ncrit particles, stopping at cells of at most ncrit particles,
+ * at leaves, and at the deepest level L at which the boundary tree has at
+ * most max_cells cells.  Its terminal cells cover every particle once; each
+ * gets the tight FP32 box of its particles, centre (min + max) / 2, half
+ * size (max - min) / 2 + m with m = fl32(fl32(max|lo| + side) 2^-16) from
+ * the key box.  Host outputs *level and *nterm may be NULL.  Valid until the
+ * next build.  Synchronises s.  Errors: BH_EINVAL (max_cells < 1),
+ * BH_ESTATE (nothing built), BH_ENOMEM. */
+int bh_boundary(bh_ctx *ctx, int32_t max_cells, int32_t *level, int64_t *nterm,
+                hipStream_t s);
+
+/* Local essential trees of the nsrc (0..64) remote contexts srcs (host
+ * array) for ctx's targets, merged into one tree below virtual cells
+ * (Sec. III.B.2); nsrc = 0 (srcs may be NULL) gives an empty one.  ctx and every source need a boundary tree and the same
+ * bh_set_box.  For each source the terminal boxes of ctx's boundary tree
+ * walk the source tree with the force walk's opening test for theta: if no
+ * box opens a terminal cell of the source's boundary tree, that boundary
+ * tree is the LET; otherwise the LET is the cells the boxes reach, opened
+ * cells with all their children and opened leaves with their particles.
+ * Walking the LET gives ctx's groups bit for bit the interaction lists of
+ * the full source tree.  Host info [nsrc][3] (may be NULL) receives per
+ * source: 1 if the boundary tree sufficed, LET cells, LET particles.  Valid
+ * until ctx's next build; the LET copies the sources, which may change
+ * afterwards.  Synchronises s.  Errors: BH_EINVAL (nsrc, theta, a source
+ * that is ctx or repeated, different boxes or devices), BH_ESTATE (missing
+ * boundary tree), BH_ECAPACITY (more than 2^29 cells), BH_ENOMEM. */
+int bh_let_build(bh_ctx *ctx, bh_ctx *const *srcs, int32_t nsrc, float theta, int64_t *info,
+                 hipStream_t s);
+
+/* Forces on ctx's particles from its own tree and from the merged LET (one
+ * walk each, the second adding to the first), written to device outputs
+ * acc [.][3] and pot [.] (either may be NULL) at row rows[i] for caller
+ * index i (device u32 [n], distinct rows; NULL: row i).  theta must be the
+ * LET's.  Errors: BH_EINVAL (theta, eps), BH_ESTATE (no build or no LET). */
+int tree_force_let(bh_ctx *ctx, float theta, float eps, const uint32_t *rows, float *acc,
+                   float *pot, hipStream_t s);
 
 /* Static description of a status code. */
 const char *bh_strerror(int status);

@@ -32,6 +32,10 @@
  *                                       -- Sec. VI.A Eq. (1) and Eq. (2),
  *                                          with Plummer softening (Sec. IV)
  *   direct O(N^2) summation             -- Sec. I.A (the theta -> 0 limit)
+ *   O7r walk of another domain's tree   -- Sec. III.B.2 (forces from a
+ *                                          remote domain's tree)
+ *   O-LET cells a remote domain needs   -- Sec. III.B.2 (local essential
+ *                                          tree; boundary-tree sufficiency)
  *
  * Floating point: every force, potential and moment is FP64.  The steps
  * whose result is an integer (keys, tree topology, the opening decision that
@@ -92,7 +96,7 @@ void orc_keys(int64_t n, const float *pos, const float *lo, float scale, uint64_
         for (int a = 0; a < 3; ++a) {
             float t = pos[3 * i + a] - lo[a];
             float u = t * scale;
-            uint32_t v = (uint32_t)u;
+            uint32_t v = u > 0.0f ? (uint32_t)u : 0u;  /* below a given box: cell 0 */
             q[a] = v > KEY_MAXQ ? KEY_MAXQ : v;
         }
         uint64_t k = 0;
@@ -313,7 +317,7 @@ void orc_keys_ph(int64_t n, const float *pos, const float *lo, float scale, uint
         for (int a = 0; a < 3; ++a) {
             float t = pos[3 * i + a] - lo[a];
             float u = t * scale;
-            uint32_t v = (uint32_t)u;
+            uint32_t v = u > 0.0f ? (uint32_t)u : 0u;  /* below a given box: cell 0 */
             X[a] = v > KEY_MAXQ ? KEY_MAXQ : v;
         }
         ph_from_axes(X, KEY_BITS);
@@ -471,13 +475,15 @@ static void interact(const double *xi, const double *src, double mj, const doubl
  * are written.  Optional diagnostics (may be NULL): ncov = particles covered
  * (accepted cells' counts + npp, must equal N) and nself = accepted cells
  * that hold a particle of the group (must be 0). */
-void orc_walk(int64_t nglist, const int64_t *glist, const int64_t *gbeg, const int64_t *gcnt,
-              const float *gc, const float *gh, int64_t ncell, const int64_t *begin,
-              const int64_t *count, const int64_t *child0, const int32_t *nchild,
-              const double *M, const double *com, const double *Q, const float *comf,
-              const float *ropen2, const float *x, const float *y, const float *z,
-              const float *m, double eps, double *acc, double *pot, int64_t *npp,
-              int64_t *npc, int64_t *ncov, int64_t *nself) {
+static void walk_groups(int64_t nglist, const int64_t *glist, const int64_t *gbeg,
+                        const int64_t *gcnt, const float *gc, const float *gh,
+                        const float *tx, const float *ty, const float *tz, int remote,
+                        int64_t ncell, const int64_t *begin, const int64_t *count,
+                        const int64_t *child0, const int32_t *nchild, const double *M,
+                        const double *com, const double *Q, const float *comf,
+                        const float *ropen2, const float *x, const float *y, const float *z,
+                        const float *m, double eps, double *acc, double *pot, int64_t *npp,
+                        int64_t *npc, int64_t *ncov, int64_t *nself) {
     double eps2 = eps * eps;
 #pragma omp parallel
     {
@@ -497,18 +503,19 @@ void orc_walk(int64_t nglist, const int64_t *glist, const int64_t *gbeg, const i
                 if (mac_accept(&comf[3 * c], ropen2[c], &gc[3 * g], &gh[3 * g])) {
                     ++cpc;
                     cov += count[c];
-                    if (begin[c] < b + nt && b < begin[c] + count[c]) ++self;
+                    if (!remote && begin[c] < b + nt && b < begin[c] + count[c]) ++self;
                     for (int64_t i = b; i < b + nt; ++i) {
-                        double xi[3] = {x[i], y[i], z[i]};
+                        double xi[3] = {tx[i], ty[i], tz[i]};
                         interact(xi, &com[3 * c], M[c], &Q[6 * c], eps2, &acc[3 * i], &pot[i], 1);
                     }
                 } else if (nchild[c] == 0) {
                     cpp += count[c];
                     for (int64_t i = b; i < b + nt; ++i) {
-                        double xi[3] = {x[i], y[i], z[i]};
+                        double xi[3] = {tx[i], ty[i], tz[i]};
                         for (int64_t j = begin[c]; j < begin[c] + count[c]; ++j) {
                             double xj[3] = {x[j], y[j], z[j]};
-                            interact(xi, xj, m[j], NULL, eps2, &acc[3 * i], &pot[i], j != i);
+                            interact(xi, xj, m[j], NULL, eps2, &acc[3 * i], &pot[i],
+                                     remote || j != i);
                         }
                     }
                 } else {
@@ -522,6 +529,66 @@ void orc_walk(int64_t nglist, const int64_t *glist, const int64_t *gbeg, const i
         }
         free(queue);
     }
+}
+
+void orc_walk(int64_t nglist, const int64_t *glist, const int64_t *gbeg, const int64_t *gcnt,
+              const float *gc, const float *gh, int64_t ncell, const int64_t *begin,
+              const int64_t *count, const int64_t *child0, const int32_t *nchild,
+              const double *M, const double *com, const double *Q, const float *comf,
+              const float *ropen2, const float *x, const float *y, const float *z,
+              const float *m, double eps, double *acc, double *pot, int64_t *npp,
+              int64_t *npc, int64_t *ncov, int64_t *nself) {
+    walk_groups(nglist, glist, gbeg, gcnt, gc, gh, x, y, z, 0, ncell, begin, count, child0,
+                nchild, M, com, Q, comf, ropen2, x, y, z, m, eps, acc, pot, npp, npc, ncov,
+                nself);
+}
+
+/* O7r -- the same walk for the groups of one tree (targets tx, ty, tz in
+ * that tree's sorted order, boxes gc, gh) through the cells and particles
+ * of another tree: the forces one domain's particles receive from another
+ * domain (Sec. III.B.2, the local essential tree computed in full).  No
+ * pair is a self pair, so every particle-particle term adds potential. */
+void orc_walk_remote(int64_t nglist, const int64_t *glist, const int64_t *gbeg,
+                     const int64_t *gcnt, const float *gc, const float *gh, const float *tx,
+                     const float *ty, const float *tz, int64_t ncell, const int64_t *begin,
+                     const int64_t *count, const int64_t *child0, const int32_t *nchild,
+                     const double *M, const double *com, const double *Q, const float *comf,
+                     const float *ropen2, const float *x, const float *y, const float *z,
+                     const float *m, double eps, double *acc, double *pot, int64_t *npp,
+                     int64_t *npc, int64_t *ncov) {
+    walk_groups(nglist, glist, gbeg, gcnt, gc, gh, tx, ty, tz, 1, ncell, begin, count, child0,
+                nchild, M, com, Q, comf, ropen2, x, y, z, m, eps, acc, pot, npp, npc, ncov,
+                NULL);
+}
+
+/* O-LET -- the cells of a source tree that a set of target boxes reaches
+ * (Sec. III.B.2: the local essential tree a remote domain needs).  Each box
+ * walks the tree from the root with the opening test of the force walk; a
+ * cell it reaches is visited, a reached cell that fails the test is opened
+ * (an internal cell's children are then reached; a leaf's particles are
+ * needed).  vis and opn are the unions over the boxes.  Returns 1 when some
+ * opened cell is flagged in bterm (a terminal cell of the source's boundary
+ * tree), i.e. the boundary tree alone does not suffice; bterm may be NULL. */
+int orc_let_mark(int64_t nbox, const float *bc, const float *bh, int64_t ncell,
+                 const int64_t *child0, const int32_t *nchild, const float *comf,
+                 const float *ropen2, const uint8_t *bterm, uint8_t *vis, uint8_t *opn) {
+    int insufficient = 0;
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ncell > 0 ? ncell : 1));
+    for (int64_t c = 0; c < ncell; ++c) vis[c] = opn[c] = 0;
+    for (int64_t k = 0; k < nbox; ++k) {
+        int64_t head = 0, tail = 0;
+        queue[tail++] = 0;
+        while (head < tail) {
+            int64_t c = queue[head++];
+            vis[c] = 1;
+            if (mac_accept(&comf[3 * c], ropen2[c], &bc[3 * k], &bh[3 * k])) continue;
+            opn[c] = 1;
+            if (bterm && bterm[c]) insufficient = 1;
+            for (int64_t ch = child0[c]; ch < child0[c] + nchild[c]; ++ch) queue[tail++] = ch;
+        }
+    }
+    free(queue);
+    return insufficient;
 }
 
 /* Direct O(N^2) sum for the listed targets: a_i = sum_{j != i} m_j r_ij /

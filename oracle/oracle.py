@@ -78,6 +78,14 @@ def lib():
         L.orc_direct.argtypes = [_i64, _f64p, _f64p, _i64, _i64p, ctypes.c_double, _f64p, _f64p]
         L.orc_expansion.argtypes = [_i64, _f64p, ctypes.c_double, _f64p, _f64p, ctypes.c_double,
                                     _f64p, _f64p]
+        L.orc_walk_remote.argtypes = [_i64, _i64p, _i64p, _i64p, _f32p, _f32p, _f32p, _f32p,
+                                      _f32p, _i64, _i64p, _i64p, _i64p, _i32p, _f64p, _f64p,
+                                      _f64p, _f32p, _f32p, _f32p, _f32p, _f32p, _f32p,
+                                      ctypes.c_double, _f64p, _f64p, _i64p, _i64p, _i64p]
+        _u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        L.orc_let_mark.argtypes = [_i64, _f32p, _f32p, _i64, _i64p, _i32p, _f32p, _f32p,
+                                   ctypes.c_void_p, _u8p, _u8p]
+        L.orc_let_mark.restype = _int
         _lib = L
     return _lib
 
@@ -248,13 +256,25 @@ class Tree:
         return np.cumsum(g)
 
 
-def build_tree(pos, mass, nleaf: int = NLEAF, ncrit: int = NCRIT, curve: str = "morton") -> Tree:
+def fixed_box(lo, side):
+    """A caller-given key box (Sec. III.B.1: every domain maps its particles
+    to keys with the one global box): lo, side, fl32(2^21 / side)."""
+    lo = np.ascontiguousarray(lo, dtype=np.float32).reshape(3)
+    side = np.float32(side)
+    return lo, side, np.float32(2097152.0 / float(side))
+
+
+def build_tree(pos, mass, nleaf: int = NLEAF, ncrit: int = NCRIT, curve: str = "morton",
+               box=None) -> Tree:
     """The whole tree of Sec. III.B.1 / Sec. I.A; curve "morton" or "ph"
-    (Peano-Hilbert, the paper's curve): the same cells in another order."""
+    (Peano-Hilbert, the paper's curve): the same cells in another order.
+    box = (lo[3], side) keys the particles in that box instead of their own
+    bounding box (a coordinate below lo takes the first cell, one at or past
+    lo + side the last)."""
     pos = _f32(pos).reshape(-1, 3)
     mass = _f32(mass).reshape(-1)
     n = pos.shape[0]
-    lo, side, scale = bbox(pos)
+    lo, side, scale = bbox(pos) if box is None else fixed_box(*box)
     keys = ph_keys(pos, lo, scale) if curve == "ph" else morton_keys(pos, lo, scale)
     perm = sort_keys(keys)
     skeys = keys[perm]

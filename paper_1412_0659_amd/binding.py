@@ -31,6 +31,9 @@ EXPORTS = {
     "group_begin": (17, np.uint32, 1), "group_count": (18, np.uint32, 1),
     "group_box": (19, np.float32, 8), "group_npp": (20, np.uint32, 1),
     "group_npc": (21, np.uint32, 1), "acc_sorted": (22, np.float32, 4),
+    "boundary_flag": (23, np.uint32, 1), "boundary_cells": (24, np.uint32, 1),
+    "boundary_box": (25, np.float32, 8), "let_origin": (26, np.uint32, 2),
+    "let_node": (27, np.uint32, 2), "let_comf": (28, np.float32, 4),
 }
 
 
@@ -64,7 +67,9 @@ SYMBOLS = ["bh_create", "bh_destroy", "tree_build", "bh_set_state", "tree_force"
            "leapfrog_step", "bh_get_state", "bh_sync", "bh_stats_get", "bh_export",
            "bh_strerror", "bh_last_error", "tree_force_vjp", "leapfrog_vjp_drift",
            "bh_state_bytes", "bh_save_state", "bh_load_state", "bh_cic_density",
-           "bh_cic_density_vjp", "tree_direct", "bh_diagnostics"]
+           "bh_cic_density_vjp", "tree_direct", "bh_diagnostics", "bh_set_box",
+           "bh_decompose", "bh_domain_extract", "tree_force_add", "bh_boundary",
+           "bh_let_build", "tree_force_let"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -108,6 +113,14 @@ def load():
                                 _vp, _vp], c_int),
         "tree_direct": ([_vp, _vp, i64, f32, _vp, _vp, _vp], c_int),
         "bh_diagnostics": ([_vp, ctypes.POINTER(ctypes.c_double), _vp], c_int),
+        "bh_set_box": ([_vp, _vp, f32], c_int),
+        "bh_decompose": ([_vp, ctypes.c_int32, f32, _vp, _vp], c_int),
+        "bh_domain_extract": ([_vp, i64, i64, _vp, _vp, _vp, _vp, _vp], c_int),
+        "tree_force_add": ([_vp, _vp, f32, f32, _vp, _vp, _vp], c_int),
+        "bh_boundary": ([_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                         ctypes.POINTER(i64), _vp], c_int),
+        "bh_let_build": ([_vp, _vp, ctypes.c_int32, f32, _vp, _vp], c_int),
+        "tree_force_let": ([_vp, f32, f32, _vp, _vp, _vp, _vp], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -291,6 +304,68 @@ def bh_cic_density_vjp(ctx, pos, mass, sel, grid, g_density, g_pos=None, g_mass=
                                           _ptr(g_mass), _stream(stream)))
 
 
+def _u32ptr(t):
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()
+            and t.dtype in (torch.int32, torch.uint32)):
+        raise TypeError("expected a contiguous 32-bit integer CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def bh_set_box(ctx, lo=None, side=1.0):
+    """Key later builds in the cube [lo, lo + side)^3 (lo None: own box)."""
+    if lo is None:
+        _check(ctx, load().bh_set_box(ctx, None, 1.0))
+        return
+    a = (ctypes.c_float * 3)(*[float(v) for v in np.asarray(lo, np.float32).reshape(3)])
+    _check(ctx, load().bh_set_box(ctx, ctypes.cast(a, _vp), float(side)))
+
+
+def bh_decompose(ctx, p, cap=1.3, stream=None) -> np.ndarray:
+    """Cuts [p + 1] of the sorted particles into p flop-balanced domains."""
+    cuts = np.zeros(int(p) + 1, np.int64)
+    _check(ctx, load().bh_decompose(ctx, int(p), float(cap), cuts.ctypes.data_as(_vp),
+                                    _stream(stream)))
+    return cuts
+
+
+def bh_domain_extract(ctx, lo, hi, pos=None, vel=None, mass=None, ids=None, stream=None):
+    _check(ctx, load().bh_domain_extract(ctx, int(lo), int(hi), _ptr(pos), _ptr(vel),
+                                         _ptr(mass), _u32ptr(ids), _stream(stream)))
+
+
+def tree_force_add(ctx, src, theta, eps, acc=None, pot=None, stream=None):
+    _check(ctx, load().tree_force_add(ctx, src, float(theta), float(eps), _ptr(acc), _ptr(pot),
+                                      _stream(stream)))
+
+
+def bh_boundary(ctx, max_cells, stream=None):
+    """Boundary tree; returns (level, number of terminal cells)."""
+    lev = ctypes.c_int32(0)
+    nt = ctypes.c_int64(0)
+    _check(ctx, load().bh_boundary(ctx, int(max_cells), ctypes.byref(lev), ctypes.byref(nt),
+                                   _stream(stream)))
+    return lev.value, nt.value
+
+
+def bh_let_build(ctx, srcs, theta, stream=None) -> np.ndarray:
+    """Merged LETs of the source contexts; returns info [nsrc][3]:
+    (boundary tree sufficed, LET cells, LET particles)."""
+    k = len(srcs)
+    arr = (_vp * max(k, 1))(*[s.value if isinstance(s, _vp) else s for s in srcs])
+    info = np.zeros((max(k, 1), 3), np.int64)
+    _check(ctx, load().bh_let_build(ctx, ctypes.cast(arr, _vp) if k else None, k, float(theta),
+                                    info.ctypes.data_as(_vp), _stream(stream)))
+    return info[:k]
+
+
+def tree_force_let(ctx, theta, eps, rows=None, acc=None, pot=None, stream=None):
+    _check(ctx, load().tree_force_let(ctx, float(theta), float(eps), _u32ptr(rows), _ptr(acc),
+                                      _ptr(pot), _stream(stream)))
+
+
 class Tree:
     """Owns one library context; methods call the C entry points."""
 
@@ -391,10 +466,62 @@ class Tree:
         st = self.stats()
         sizes = {"keys": st["n"], "perm": st["n"], "acc_sorted": st["n"], "box": 5,
                  "level_start": 23}
-        if name.startswith("cell") or name.startswith("mom"):
+        if name.startswith("cell") or name.startswith("mom") or name == "boundary_flag":
             count = st["ncells"]
         elif name.startswith("group"):
             count = st["ngroups"]
+        elif name.startswith("boundary"):
+            count = self.nterm
+        elif name.startswith("let"):
+            count = self.let_cells
         else:
             count = sizes[name]
         return bh_export(self.ctx, name, count)
+
+    # ---- several domains on one device (Sec. III.B)
+
+    def set_box(self, lo=None, side=1.0):
+        bh_set_box(self.ctx, lo, side)
+
+    def decompose(self, p, cap=1.3) -> np.ndarray:
+        return bh_decompose(self.ctx, p, cap)
+
+    def extract(self, lo, hi):
+        """Particles of sorted slots [lo, hi): (pos, vel, mass, ids) tensors."""
+        import torch
+        k = int(hi) - int(lo)
+        pos = torch.empty((k, 3), dtype=torch.float32, device="cuda")
+        vel = torch.empty((k, 3), dtype=torch.float32, device="cuda")
+        mass = torch.empty((k,), dtype=torch.float32, device="cuda")
+        ids = torch.empty((k,), dtype=torch.int32, device="cuda")
+        bh_domain_extract(self.ctx, lo, hi, pos, vel, mass, ids)
+        return pos, vel, mass, ids
+
+    def force_add(self, src, theta, eps, acc, pot):
+        tree_force_add(self.ctx, src.ctx, theta, eps, acc, pot)
+
+    def boundary(self, max_cells):
+        self.boundary_level, self.nterm = bh_boundary(self.ctx, max_cells)
+        return self.boundary_level, self.nterm
+
+    def let_build(self, srcs, theta) -> np.ndarray:
+        info = bh_let_build(self.ctx, [s.ctx for s in srcs], theta)
+        self.let_cells = int(self.let_virtual(len(srcs)) + info[:, 1].sum()) if srcs else 0
+        return info
+
+    @staticmethod
+    def let_virtual(k) -> int:
+        """Virtual cells above k LET roots (levels of at most 8 children)."""
+        sizes = [k]
+        while sizes[0] > 1 or len(sizes) == 1:
+            sizes.insert(0, (sizes[0] + 7) // 8)
+        return sum(sizes[:-1])
+
+    def force_let(self, theta, eps, rows=None, acc=None, pot=None):
+        import torch
+        if acc is None:
+            acc = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
+        if pot is None:
+            pot = torch.empty((self.n,), dtype=torch.float32, device="cuda")
+        tree_force_let(self.ctx, theta, eps, rows, acc, pot)
+        return acc, pot

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "bh_internal.h"
 
@@ -57,6 +58,11 @@ void free_all(bh_ctx *c) {
     Groups &g = c->groups;
     f(g.flag); f(g.scan); f(g.begin); f(g.count_dev); f(g.box); f(g.npp); f(g.npc);
     f(c->lcell); f(c->gsrc); f(c->usort); f(c->leafof); f(c->cic); f(c->inv); f(c->diag);
+    Boundary &b = c->bnd;
+    f(b.flag); f(b.scan); f(b.ids); f(b.box); f(b.lvl); f(b.part);
+    Let &t = c->let;
+    f(t.wA); f(t.P0); f(t.P1); f(t.P2); f(t.xyzm); f(t.wN); f(t.origin);
+    f(t.cmark); f(t.cscan); f(t.pmark); f(t.pscan); f(t.spart); f(t.word);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
 }
@@ -72,6 +78,7 @@ int check_status(bh_ctx *c) {
     if (st & kStNonFinite) return fail(c, BH_ENONFINITE, "non-finite position or velocity");
     if (st & kStMass) return fail(c, BH_EMASS, "mass <= 0 or not finite");
     if (st & kStIndex) return fail(c, BH_EINVAL, "target index outside [0, n)");
+    if (st & kStOutside) return fail(c, BH_EINVAL, "particle outside the box set by bh_set_box");
     return fail(c, BH_ECAPACITY, "cell or stack capacity exceeded");
 }
 
@@ -91,6 +98,9 @@ void rebuild(bh_ctx *c, uint32_t n, hipStream_t s) {
     c->ev_rec[0] = c->ev_rec[1] = c->ev_rec[2] = c->ev_rec[3] = true;
     c->built = true;
     c->have_acc = false;
+    c->counts_valid = false;
+    c->bnd.valid = false;
+    c->let.valid = false;
 }
 
 void force(bh_ctx *c, float theta, float eps, hipStream_t s) {
@@ -98,8 +108,27 @@ void force(bh_ctx *c, float theta, float eps, hipStream_t s) {
     launch_walk(c, eps, s);
     launch_totals(c, (uint32_t)c->n, s);
     c->have_acc = true;
+    c->counts_valid = true;
     c->acc_theta = theta;
     c->acc_eps = eps;
+}
+
+// lazily sized device buffers of the multi-domain calls
+template <class T>
+bool grow(T **p, int64_t &cap, int64_t need, std::string &err) {
+    if (*p && cap >= need) return true;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    cap = 0;
+    if (!dalloc(p, (size_t)need, err)) return false;
+    cap = need;
+    return true;
+}
+
+bool same_box(const bh_ctx *a, const bh_ctx *b) {
+    return a->fixed_box && b->fixed_box && a->box_lo[0] == b->box_lo[0] &&
+           a->box_lo[1] == b->box_lo[1] && a->box_lo[2] == b->box_lo[2] &&
+           a->box_side == b->box_side;
 }
 
 int check_n(bh_ctx *c, int64_t n) {
@@ -323,7 +352,7 @@ int bh_stats_get(bh_ctx *c, bh_stats *out, hipStream_t s) {
         out->ngroups = ng;
         for (int l = 0; l < kLevels; ++l)
             if (ls[l + 1] > ls[l]) out->depth = l;
-        if (c->have_acc) {
+        if (c->counts_valid) {
             out->n_pp = (int64_t)tot[0];
             out->n_pc = (int64_t)tot[1];
         }
@@ -386,6 +415,22 @@ int bh_export(bh_ctx *c, int array, void *dst, int64_t cap_bytes, int64_t *nbyte
         case BH_ARR_GROUP_NPP: src = g.npp; bytes = 4 * (size_t)ng; break;
         case BH_ARR_GROUP_NPC: src = g.npc; bytes = 4 * (size_t)ng; break;
         case BH_ARR_ACC_SORTED: src = c->acc; bytes = 16 * n; break;
+        case BH_ARR_BOUNDARY_FLAG:
+        case BH_ARR_BOUNDARY_CELLS:
+        case BH_ARR_BOUNDARY_BOX:
+            if (!c->bnd.valid) return fail(c, BH_ESTATE, "no boundary tree");
+            if (array == BH_ARR_BOUNDARY_FLAG) { src = c->bnd.flag; bytes = 4 * nc; }
+            if (array == BH_ARR_BOUNDARY_CELLS) { src = c->bnd.ids; bytes = 4 * (size_t)c->bnd.nterm; }
+            if (array == BH_ARR_BOUNDARY_BOX) { src = c->bnd.box; bytes = 32 * (size_t)c->bnd.nterm; }
+            break;
+        case BH_ARR_LET_ORIGIN:
+        case BH_ARR_LET_NODE:
+        case BH_ARR_LET_COMF:
+            if (!c->let.valid) return fail(c, BH_ESTATE, "no local essential tree");
+            if (array == BH_ARR_LET_ORIGIN) { src = c->let.origin; bytes = 8 * (size_t)c->let.ncell; }
+            if (array == BH_ARR_LET_NODE) { src = c->let.wN; bytes = 8 * (size_t)c->let.ncell; }
+            if (array == BH_ARR_LET_COMF) { src = c->let.wA; bytes = 16 * (size_t)c->let.ncell; }
+            break;
         default: return fail(c, BH_EINVAL, "unknown export id");
     }
     if ((int64_t)bytes > cap_bytes) return fail(c, BH_ECAPACITY, "export buffer too small");
@@ -520,6 +565,305 @@ int bh_cic_density_vjp(bh_ctx *c, const float *pos, const float *mass, const uin
         return fail(c, BH_EINVAL, "bad arguments");
     launch_cic_vjp(pos, mass, sel, (uint32_t)n, grid->r_min, grid->r_max, grid->n_r, grid->n_phi,
                    g_density, g_pos, g_mass, s);
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+int bh_set_box(bh_ctx *c, const float *lo, float side) {
+    if (!c) return BH_EINVAL;
+    if (!lo) {
+        c->fixed_box = false;
+        return BH_OK;
+    }
+    if (!std::isfinite(lo[0]) || !std::isfinite(lo[1]) || !std::isfinite(lo[2]) ||
+        !std::isfinite(side) || !(side > 0.f))
+        return fail(c, BH_EINVAL, "box corner must be finite and side > 0");
+    c->fixed_box = true;
+    c->box_lo[0] = lo[0];
+    c->box_lo[1] = lo[1];
+    c->box_lo[2] = lo[2];
+    c->box_side = side;
+    return BH_OK;
+}
+
+int bh_decompose(bh_ctx *c, int32_t p, float cap, int64_t *cuts, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!cuts) return fail(c, BH_EINVAL, "null pointer");
+    if (!c->built) return fail(c, BH_ESTATE, "bh_decompose before tree_build");
+    if (!c->counts_valid) return fail(c, BH_ESTATE, "bh_decompose needs a force walk");
+    const int64_t n = c->n;
+    if (p < 1 || p > n) return fail(c, BH_EINVAL, "p must be in [1, n]");
+    if (!std::isfinite(cap) || !(cap >= 1.f)) return fail(c, BH_EINVAL, "cap must be >= 1");
+    const int64_t C = (int64_t)std::floor((double)cap * (double)n / (double)p);
+    if (C * (int64_t)p < n) return fail(c, BH_EINVAL, "cap * n / p cannot hold n particles");
+    BH_HIP(c, hipStreamSynchronize(s));
+    uint32_t ng = 0;
+    BH_HIP(c, hipMemcpy(&ng, c->groups.count_dev, sizeof(ng), hipMemcpyDeviceToHost));
+    std::string err;
+    uint32_t *hb = new (std::nothrow) uint32_t[3 * (size_t)ng + 1];
+    if (!hb) return fail(c, BH_ENOMEM, "host allocation");
+    uint32_t *npp = hb + ng + 1, *npc = npp + ng;
+    hipError_t e = hipMemcpy(hb, c->groups.begin, 4 * ((size_t)ng + 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(npp, c->groups.npp, 4 * (size_t)ng, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(npc, c->groups.npc, 4 * (size_t)ng, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        delete[] hb;
+        BH_HIP(c, e);
+    }
+    // running cost S_i of the particles before sorted slot i; cut j is the
+    // first i with S_i p >= W j (exact in 128-bit integers)
+    __int128 W = 0;
+    for (uint32_t g = 0; g < ng; ++g)
+        W += (__int128)(hb[g + 1] - hb[g]) * (23 * (__int128)npp[g] + 65 * (__int128)npc[g]);
+    cuts[0] = 0;
+    __int128 S = 0;
+    int32_t j = 1;
+    for (uint32_t g = 0; g < ng && j < p; ++g) {
+        const __int128 w = 23 * (__int128)npp[g] + 65 * (__int128)npc[g];
+        for (uint32_t i = hb[g]; i < hb[g + 1] && j < p; ++i) {
+            while (j < p && S * p >= W * j) cuts[j++] = i;
+            S += w;
+        }
+    }
+    while (j < p) {
+        if (S * p >= W * j) cuts[j] = n;
+        ++j;
+    }
+    delete[] hb;
+    for (int32_t k = 1; k < p; ++k) {
+        const int64_t lo = std::max(cuts[k - 1], n - (int64_t)(p - k) * C);
+        const int64_t hi = std::min(cuts[k - 1] + C, n);
+        cuts[k] = std::min(std::max(cuts[k], lo), hi);
+    }
+    cuts[p] = n;
+    return check_status(c);
+}
+
+int bh_domain_extract(bh_ctx *c, int64_t lo, int64_t hi, float *pos, float *vel, float *mass,
+                      uint32_t *ids, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!c->built) return fail(c, BH_ESTATE, "bh_domain_extract before tree_build");
+    if (lo < 0 || hi < lo || hi > c->n) return fail(c, BH_EINVAL, "need 0 <= lo <= hi <= n");
+    if (hi > lo) launch_range_out(c, (uint32_t)lo, (uint32_t)(hi - lo), pos, vel, mass, ids, s);
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+int tree_force_add(bh_ctx *c, bh_ctx *src, float theta, float eps, float *acc, float *pot,
+                   hipStream_t s) {
+    if (!c || !src) return BH_EINVAL;
+    if (src == c) return fail(c, BH_EINVAL, "the source must be another context");
+    if (!valid_theta(theta)) return fail(c, BH_EINVAL, "theta must be in (0, 1]");
+    if (!valid_eps(eps)) return fail(c, BH_EINVAL, "eps must be finite and >= 0");
+    if (!c->built || !src->built) return fail(c, BH_ESTATE, "tree_force_add before tree_build");
+    if (src->device != c->device) return fail(c, BH_EINVAL, "contexts on different devices");
+    launch_walk_prep(src, theta, s);
+    launch_walk_view(c, own_view(src), eps, true, false, s);
+    if (acc || pot) launch_unsort_add(c, acc, pot, (uint32_t)c->n, s);
+    c->have_acc = false;
+    c->counts_valid = false;
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+int bh_boundary(bh_ctx *c, int32_t max_cells, int32_t *level, int64_t *nterm, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!c->built) return fail(c, BH_ESTATE, "bh_boundary before tree_build");
+    if (max_cells < 1) return fail(c, BH_EINVAL, "max_cells must be >= 1");
+    Boundary &b = c->bnd;
+    std::string err;
+    const int64_t cap = c->cap_cells + 1;
+    int64_t c1 = b.flag ? cap : 0, c2 = c1, c3 = c1, c4 = c1, c5 = c1, c6 = c1;
+    const int64_t plen = scan_part_len(cap);
+    if (!b.flag) {
+        if (!grow(&b.flag, c1, cap, err) || !grow(&b.scan, c2, cap, err) ||
+            !grow(&b.ids, c3, cap, err) || !grow(&b.box, c4, 2 * cap, err) ||
+            !grow(&b.lvl, c5, kLevels, err) || !grow(&b.part, c6, plen, err))
+            return fail(c, BH_ENOMEM, err);
+    }
+    b.valid = false;
+    launch_bnd_flags(c, s);
+    uint32_t lvl[kLevels];
+    float box[5];
+    BH_HIP(c, hipStreamSynchronize(s));
+    BH_HIP(c, hipMemcpy(lvl, b.lvl, sizeof(lvl), hipMemcpyDeviceToHost));
+    BH_HIP(c, hipMemcpy(box, c->box, sizeof(box), hipMemcpyDeviceToHost));
+    int64_t tot = 0;
+    int L = -1;
+    for (int l = 0; l < kLevels; ++l) {
+        if (tot + (int64_t)lvl[l] > (int64_t)max_cells) break;
+        tot += lvl[l];
+        L = l;
+    }
+    if (L < 0) return fail(c, BH_EINVAL, "max_cells < 1");
+    const uint32_t nc = cell_count(c, s);
+    launch_bnd_terminal(c, L, s);
+    launch_exclusive_scan(b.scan, b.scan, nc + 1, b.part, s);
+    uint32_t nt = 0;
+    BH_HIP(c, hipStreamSynchronize(s));
+    BH_HIP(c, hipMemcpy(&nt, b.scan + nc, sizeof(nt), hipMemcpyDeviceToHost));
+    // margin: 2^-16 of the largest coordinate magnitude the box allows
+    float mabs = std::max(std::fabs(box[0]), std::max(std::fabs(box[1]), std::fabs(box[2])));
+    float r = mabs + box[3];
+    b.margin = r * 0x1p-16f;
+    launch_bnd_boxes(c, nc, nt, s);
+    BH_HIP(c, hipGetLastError());
+    b.level = L;
+    b.nterm = nt;
+    b.valid = true;
+    if (level) *level = L;
+    if (nterm) *nterm = nt;
+    BH_HIP(c, hipStreamSynchronize(s));
+    return check_status(c);
+}
+
+int bh_let_build(bh_ctx *c, bh_ctx *const *srcs, int32_t nsrc, float theta, int64_t *info,
+                 hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if ((!srcs && nsrc) || nsrc < 0 || nsrc > 64)
+        return fail(c, BH_EINVAL, "need 0 <= nsrc <= 64 sources");
+    if (!valid_theta(theta)) return fail(c, BH_EINVAL, "theta must be in (0, 1]");
+    if (!c->built || !c->bnd.valid) return fail(c, BH_ESTATE, "target needs a boundary tree");
+    if (nsrc == 0) {  // a single domain: nothing remote
+        c->let.ncell = c->let.npart = 0;
+        c->let.nsrc = 0;
+        c->let.theta = theta;
+        c->let.valid = true;
+        return BH_OK;
+    }
+    for (int32_t k = 0; k < nsrc; ++k) {
+        const bh_ctx *src = srcs[k];
+        if (!src || src == c) return fail(c, BH_EINVAL, "sources must be other contexts");
+        if (!src->built || !src->bnd.valid)
+            return fail(c, BH_ESTATE, "every source needs a boundary tree");
+        if (src->device != c->device) return fail(c, BH_EINVAL, "contexts on different devices");
+        if (!same_box(c, src)) return fail(c, BH_EINVAL, "all domains need the same bh_set_box");
+        for (int32_t q = 0; q < k; ++q)
+            if (srcs[q] == src) return fail(c, BH_EINVAL, "a source is listed twice");
+    }
+    Let &t = c->let;
+    t.valid = false;
+    // virtual cells above the LET roots: levels of at most 8 children each
+    int64_t lv[4] = {nsrc, 0, 0, 0};
+    int nlv = 1;
+    while (lv[0] > 1 || nlv == 1) {
+        for (int q = nlv; q > 0; --q) lv[q] = lv[q - 1];
+        lv[0] = (lv[1] + 7) / 8;
+        ++nlv;
+    }
+    int64_t nv = 0;
+    for (int q = 0; q + 1 < nlv; ++q) nv += lv[q];
+    // sizes
+    std::vector<uint32_t> ncs((size_t)nsrc);
+    int64_t need_c = nv, need_p = 0, max_c = 0, max_p = 0;
+    for (int32_t k = 0; k < nsrc; ++k) {
+        ncs[(size_t)k] = cell_count(srcs[k], s);
+        need_c += ncs[(size_t)k];
+        need_p += srcs[k]->n;
+        max_c = std::max<int64_t>(max_c, ncs[(size_t)k]);
+        max_p = std::max<int64_t>(max_p, srcs[k]->n);
+    }
+    if (need_c >= (int64_t(1) << 29) || need_p >= (int64_t(1) << 31))
+        return fail(c, BH_ECAPACITY, "local essential tree too large");
+    std::string err;
+    int64_t cc = t.cell_cap, c2 = cc, c3 = cc, c4 = cc, c5 = cc, c6 = cc, c7 = 2 * cc;
+    int64_t pc = t.part_cap;
+    if (!grow(&t.wA, cc, need_c, err) || !grow(&t.P0, c2, need_c, err) ||
+        !grow(&t.P1, c3, need_c, err) || !grow(&t.P2, c4, need_c, err) ||
+        !grow(&t.wN, c5, need_c, err) || !grow(&t.origin, c7, 2 * need_c, err) ||
+        !grow(&t.xyzm, pc, std::max<int64_t>(need_p, 1), err)) {
+        t.cell_cap = t.part_cap = 0;
+        return fail(c, BH_ENOMEM, err);
+    }
+    (void)c6;
+    t.cell_cap = need_c;
+    t.part_cap = std::max<int64_t>(need_p, 1);
+    int64_t s1 = t.scr_cells, s2 = s1, s3 = t.scr_parts, s4 = s3, s5 = t.part_len, s6 = 1;
+    const int64_t plen = scan_part_len(std::max(max_c, max_p) + 1);
+    if (!grow(&t.cmark, s1, max_c + 1, err) || !grow(&t.cscan, s2, max_c + 1, err) ||
+        !grow(&t.pmark, s3, max_p + 1, err) || !grow(&t.pscan, s4, max_p + 1, err) ||
+        !grow(&t.spart, s5, plen, err) || (!t.word && !grow(&t.word, s6, 1, err))) {
+        t.scr_cells = t.scr_parts = t.part_len = 0;
+        return fail(c, BH_ENOMEM, err);
+    }
+    t.scr_cells = max_c + 1;
+    t.scr_parts = max_p + 1;
+    t.part_len = plen;
+
+    uint32_t cbase = (uint32_t)(nv + nsrc), pbase = 0;
+    for (int32_t k = 0; k < nsrc; ++k) {
+        bh_ctx *src = srcs[k];
+        const uint32_t nc = ncs[(size_t)k];
+        launch_walk_prep(src, theta, s);
+        launch_let_mark(c, src, nc, s);
+        uint32_t word = 0;
+        BH_HIP(c, hipStreamSynchronize(s));
+        BH_HIP(c, hipMemcpy(&word, t.word, sizeof(word), hipMemcpyDeviceToHost));
+        const bool boundary_only = word == 0u;
+        launch_let_keep(c, src, nc, boundary_only, s);
+        uint32_t kc = 0, kp = 0;
+        BH_HIP(c, hipStreamSynchronize(s));
+        BH_HIP(c, hipMemcpy(&kc, t.cscan + nc, sizeof(kc), hipMemcpyDeviceToHost));
+        BH_HIP(c, hipMemcpy(&kp, t.pscan + src->n, sizeof(kp), hipMemcpyDeviceToHost));
+        launch_let_emit(c, src, nc, k, boundary_only, (uint32_t)(nv + k), cbase, pbase, s);
+        BH_HIP(c, hipGetLastError());
+        if (info) {
+            info[3 * k] = boundary_only ? 1 : 0;
+            info[3 * k + 1] = kc;
+            info[3 * k + 2] = kp;
+        }
+        cbase += kc - 1u;
+        pbase += kp;
+    }
+    // the virtual cells: never accepted (r_open^2 = +inf), children contiguous
+    std::vector<float4> vA((size_t)nv), vz((size_t)nv);
+    std::vector<uint2> vN((size_t)nv);
+    std::vector<uint32_t> vo(2 * (size_t)nv, kNone);
+    int64_t off = 0;
+    for (int q = 0; q + 1 < nlv; ++q) {
+        const int64_t next = off + lv[q];
+        for (int64_t i = 0; i < lv[q]; ++i) {
+            const int64_t f = 8 * i, cnt = std::min<int64_t>(8, lv[q + 1] - f);
+            vA[(size_t)(off + i)] = make_float4(0.f, 0.f, 0.f, INFINITY);
+            vz[(size_t)(off + i)] = make_float4(0.f, 0.f, 0.f, 0.f);
+            vN[(size_t)(off + i)] = make_uint2((uint32_t)(next + f), (uint32_t)cnt);
+        }
+        off = next;
+    }
+    BH_HIP(c, hipStreamSynchronize(s));
+    BH_HIP(c, hipMemcpy(t.wA, vA.data(), 16 * (size_t)nv, hipMemcpyHostToDevice));
+    BH_HIP(c, hipMemcpy(t.P0, vz.data(), 16 * (size_t)nv, hipMemcpyHostToDevice));
+    BH_HIP(c, hipMemcpy(t.P1, vz.data(), 16 * (size_t)nv, hipMemcpyHostToDevice));
+    BH_HIP(c, hipMemcpy(t.P2, vz.data(), 16 * (size_t)nv, hipMemcpyHostToDevice));
+    BH_HIP(c, hipMemcpy(t.wN, vN.data(), 8 * (size_t)nv, hipMemcpyHostToDevice));
+    BH_HIP(c, hipMemcpy(t.origin, vo.data(), 8 * (size_t)nv, hipMemcpyHostToDevice));
+    t.ncell = cbase;
+    t.npart = pbase;
+    t.nsrc = nsrc;
+    t.theta = theta;
+    t.valid = true;
+    return check_status(c);
+}
+
+int tree_force_let(bh_ctx *c, float theta, float eps, const uint32_t *rows, float *acc,
+                   float *pot, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!valid_theta(theta)) return fail(c, BH_EINVAL, "theta must be in (0, 1]");
+    if (!valid_eps(eps)) return fail(c, BH_EINVAL, "eps must be finite and >= 0");
+    if (!c->built) return fail(c, BH_ESTATE, "tree_force_let before tree_build");
+    if (!c->let.valid) return fail(c, BH_ESTATE, "tree_force_let before bh_let_build");
+    if (theta != c->let.theta) return fail(c, BH_EINVAL, "theta differs from the LET's");
+    force(c, theta, eps, s);
+    SrcView v;
+    v.wA = c->let.wA; v.wN = c->let.wN;
+    v.P0 = c->let.P0; v.P1 = c->let.P1; v.P2 = c->let.P2;
+    v.xyzm = c->let.xyzm;
+    if (c->let.ncell) {
+        launch_walk_view(c, v, eps, true, true, s);
+        launch_totals(c, (uint32_t)c->n, s);
+    }
+    if (acc || pot) launch_unsort(c, acc, pot, (uint32_t)c->n, s, rows);
+    c->have_acc = false;  // acc holds local + remote forces
     BH_HIP(c, hipGetLastError());
     return BH_OK;
 }

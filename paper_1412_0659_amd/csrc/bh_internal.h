@@ -28,6 +28,7 @@ constexpr uint32_t kStNonFinite = 1u;
 constexpr uint32_t kStMass = 2u;
 constexpr uint32_t kStOverflow = 4u;
 constexpr uint32_t kStIndex = 8u;       // a target index outside [0, n)
+constexpr uint32_t kStOutside = 16u;    // a particle outside the caller-given key box
 
 // Particle state in sorted (Morton) order, structure of arrays.
 struct State {
@@ -59,6 +60,44 @@ struct Groups {
     uint32_t *count_dev;    // [1] number of groups
     float4 *box;            // [2 * n] centre, half size
     uint32_t *npp, *npc;    // [n]
+};
+
+// Boundary tree of a domain (Sec. III.B.2): the cells reached from the root
+// through cells of more than ncrit particles, down to level `level`;
+// terminal cells (level `level`, at most ncrit particles, or leaves) cover
+// every particle once.
+struct Boundary {
+    bool valid = false;
+    int level = -1;
+    uint32_t nterm = 0;
+    float margin = 0.f;        // widening of the terminal boxes
+    uint32_t *flag = nullptr;  // [cap_cells + 1] bit 0: in the boundary tree, bit 1: terminal
+    uint32_t *scan = nullptr;  // [cap_cells + 1] exclusive scan of the terminal bits
+    uint32_t *ids = nullptr;   // [cap_cells] terminal cells in cell order
+    float4 *box = nullptr;     // [2 cap_cells] centre, half size (widened) of each
+    uint32_t *lvl = nullptr;   // [kLevels] boundary cells per level
+    uint32_t *part = nullptr;  // scan partials
+};
+
+// Local essential trees of remote domains merged under virtual cells
+// (Sec. III.B.2), plus the scratch of their construction.
+struct Let {
+    bool valid = false;
+    float theta = 0.f;
+    int nsrc = 0;
+    uint32_t ncell = 0, npart = 0;
+    int64_t cell_cap = 0, part_cap = 0;
+    float4 *wA = nullptr, *P0 = nullptr, *P1 = nullptr, *P2 = nullptr, *xyzm = nullptr;
+    uint2 *wN = nullptr;
+    uint32_t *origin = nullptr;  // [cell_cap][2] (source, source cell); kNone for virtual
+    // per-source scratch, sized to the largest source
+    int64_t scr_cells = 0, scr_parts = 0, part_len = 0;
+    uint32_t *cmark = nullptr;  // [cells + 1] bit 0 accepted, 1 opened, 2 reached
+    uint32_t *cscan = nullptr;  // [cells + 1] kept cells, scanned
+    uint32_t *pmark = nullptr;  // [parts + 1] particles of opened leaves
+    uint32_t *pscan = nullptr;  // [parts + 1]
+    uint32_t *spart = nullptr;  // scan partials
+    uint32_t *word = nullptr;   // [1] a terminal boundary cell was opened
 };
 
 struct Sort {
@@ -102,7 +141,13 @@ struct bh_ctx {
     uint32_t *inv = nullptr;     // [n] sorted slot of each caller index (direct sum)
     double *diag = nullptr;      // [kDiagBlocks + 1][kDiagN] diagnostics partials, result
 
+    bh::Boundary bnd{};
+    bh::Let let{};
+
     bool built = false, have_acc = false;
+    bool counts_valid = false;  // npp / npc / totals describe a walk of the current groups
+    bool fixed_box = false;     // keys relative to a caller-given box (bh_set_box)
+    float box_lo[3] = {0.f, 0.f, 0.f}, box_side = 1.f;
     float acc_theta = 0.f, acc_eps = 0.f;
     int walk_grid = 0;
     bool walk_small_stack = false;  // test hook: 128-entry LDS stack window
@@ -155,8 +200,34 @@ void launch_groups(bh_ctx *c, uint32_t n, hipStream_t st);
 void launch_moments(bh_ctx *c, hipStream_t st);
 void launch_walk_prep(bh_ctx *c, float theta, hipStream_t st);
 
+// let.hip: boundary trees and local essential trees (Sec. III.B.2); nc is
+// the cell count of the tree the launcher reads (cell_count)
+void launch_bnd_flags(bh_ctx *c, hipStream_t st);                // -> bnd.flag bit 0, bnd.lvl
+void launch_bnd_terminal(bh_ctx *c, int level, hipStream_t st);  // -> flag bit 1, scan input
+void launch_bnd_boxes(bh_ctx *c, uint32_t nc, uint32_t nterm, hipStream_t st);  // -> ids, box
+void launch_let_mark(bh_ctx *tgt, const bh_ctx *src, uint32_t nc, hipStream_t st);
+void launch_let_keep(bh_ctx *tgt, const bh_ctx *src, uint32_t nc, bool boundary_only,
+                     hipStream_t st);
+void launch_let_emit(bh_ctx *tgt, const bh_ctx *src, uint32_t nc, int src_index,
+                     bool boundary_only, uint32_t root_slot, uint32_t cbase, uint32_t pbase,
+                     hipStream_t st);
+uint32_t cell_count(const bh_ctx *c, hipStream_t st);  // synchronises st, reads the count
+
 // walk.hip
+// The cells and particles a walk reads: a context's own tree, another
+// domain's tree, or a merged local essential tree.
+struct SrcView {
+    const float4 *wA;   // com, r_open^2 (prepared for the walk's theta)
+    const uint2 *wN;    // internal: (child0, nchild); leaf: (first, count | kLeafBit)
+    const float4 *P0, *P1, *P2;
+    const float4 *xyzm;  // particles the leaves index
+};
+SrcView own_view(const bh_ctx *c);
 void launch_walk(bh_ctx *c, float eps, hipStream_t st);
+// c's groups walk the tree v; remote: no self pairs (v is not c's own tree);
+// accum: forces and counts add to c->acc, npp, npc
+void launch_walk_view(bh_ctx *c, const SrcView &v, float eps, bool remote, bool accum,
+                      hipStream_t st);
 int walk_blocks_per_cu();
 
 // integrate.hip
@@ -164,8 +235,12 @@ void launch_ingest(bh_ctx *c, const float *pos, const float *vel, const float *m
                    hipStream_t st);
 void launch_kick(bh_ctx *c, float h, uint32_t n, hipStream_t st);
 void launch_kick_drift(bh_ctx *c, float h, float dt, uint32_t n, hipStream_t st);
-void launch_unsort(bh_ctx *c, float *acc, float *pot, uint32_t n, hipStream_t st);
+void launch_unsort(bh_ctx *c, float *acc, float *pot, uint32_t n, hipStream_t st,
+                   const uint32_t *rows = nullptr);
+void launch_unsort_add(bh_ctx *c, float *acc, float *pot, uint32_t n, hipStream_t st);
 void launch_state_out(bh_ctx *c, float *pos, float *vel, uint32_t n, hipStream_t st);
+void launch_range_out(bh_ctx *c, uint32_t lo, uint32_t cnt, float *pos, float *vel, float *mass,
+                      uint32_t *ids, hipStream_t st);
 void launch_totals(bh_ctx *c, uint32_t n, hipStream_t st);
 void launch_count_leaves(bh_ctx *c, hipStream_t st);
 void launch_diagnostics(bh_ctx *c, hipStream_t st);  // result at diag + kDiagBlocks * kDiagN

@@ -108,15 +108,18 @@ void launch_kick_drift(bh_ctx *c, float h, float dt, uint32_t n, hipStream_t st)
                        (const float4 *)c->acc, n, h, dt);
 }
 
-// sorted acceleration + potential -> caller order
+// sorted acceleration + potential -> caller order (rows: output row of each
+// caller index, or null for the identity)
 __global__ __launch_bounds__(256) void k_unsort(const float4 *__restrict__ acc,
                                                 const uint32_t *__restrict__ cid, uint32_t n,
+                                                const uint32_t *__restrict__ rows,
                                                 float *__restrict__ out_acc,
                                                 float *__restrict__ out_pot) {
     uint32_t i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     float4 a = acc[i];
     uint32_t p = cid[i];
+    if (rows) p = rows[p];
     if (out_acc) {
         out_acc[3 * (size_t)p] = a.x;
         out_acc[3 * (size_t)p + 1] = a.y;
@@ -125,9 +128,32 @@ __global__ __launch_bounds__(256) void k_unsort(const float4 *__restrict__ acc,
     if (out_pot) out_pot[p] = a.w;
 }
 
-void launch_unsort(bh_ctx *c, float *acc, float *pot, uint32_t n, hipStream_t st) {
+// sorted acceleration + potential added to caller-order outputs
+__global__ __launch_bounds__(256) void k_unsort_add(const float4 *__restrict__ acc,
+                                                    const uint32_t *__restrict__ cid, uint32_t n,
+                                                    float *__restrict__ out_acc,
+                                                    float *__restrict__ out_pot) {
+    uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float4 a = acc[i];
+    uint32_t p = cid[i];
+    if (out_acc) {
+        out_acc[3 * (size_t)p] += a.x;
+        out_acc[3 * (size_t)p + 1] += a.y;
+        out_acc[3 * (size_t)p + 2] += a.z;
+    }
+    if (out_pot) out_pot[p] += a.w;
+}
+
+void launch_unsort_add(bh_ctx *c, float *acc, float *pot, uint32_t n, hipStream_t st) {
+    hipLaunchKernelGGL(k_unsort_add, dim3(cdiv(n, 256)), dim3(256), 0, st,
+                       (const float4 *)c->acc, (const uint32_t *)c->st[c->cur].cid, n, acc, pot);
+}
+
+void launch_unsort(bh_ctx *c, float *acc, float *pot, uint32_t n, hipStream_t st,
+                   const uint32_t *rows) {
     hipLaunchKernelGGL(k_unsort, dim3(cdiv(n, 256)), dim3(256), 0, st, (const float4 *)c->acc,
-                       (const uint32_t *)c->st[c->cur].cid, n, acc, pot);
+                       (const uint32_t *)c->st[c->cur].cid, n, rows, acc, pot);
 }
 
 __global__ __launch_bounds__(256) void k_state_out(State s, uint32_t n, float *__restrict__ pos,
@@ -150,6 +176,36 @@ __global__ __launch_bounds__(256) void k_state_out(State s, uint32_t n, float *_
 void launch_state_out(bh_ctx *c, float *pos, float *vel, uint32_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_state_out, dim3(cdiv(n, 256)), dim3(256), 0, st, c->st[c->cur], n, pos,
                        vel);
+}
+
+// sorted slots [lo, lo + cnt) -> packed outputs in sorted order: the
+// particles of one domain of the curve
+__global__ __launch_bounds__(256) void k_range_out(State s, uint32_t lo, uint32_t cnt,
+                                                   float *__restrict__ pos,
+                                                   float *__restrict__ vel,
+                                                   float *__restrict__ mass,
+                                                   uint32_t *__restrict__ ids) {
+    uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= cnt) return;
+    uint32_t i = lo + k;
+    if (pos) {
+        pos[3 * (size_t)k] = s.x[i];
+        pos[3 * (size_t)k + 1] = s.y[i];
+        pos[3 * (size_t)k + 2] = s.z[i];
+    }
+    if (vel) {
+        vel[3 * (size_t)k] = s.vx[i];
+        vel[3 * (size_t)k + 1] = s.vy[i];
+        vel[3 * (size_t)k + 2] = s.vz[i];
+    }
+    if (mass) mass[k] = s.m[i];
+    if (ids) ids[k] = s.cid[i];
+}
+
+void launch_range_out(bh_ctx *c, uint32_t lo, uint32_t cnt, float *pos, float *vel, float *mass,
+                      uint32_t *ids, hipStream_t st) {
+    hipLaunchKernelGGL(k_range_out, dim3(cdiv(cnt, 256)), dim3(256), 0, st, c->st[c->cur], lo,
+                       cnt, pos, vel, mass, ids);
 }
 
 // Conserved quantities of the state, FP64: total mass, kinetic energy,

@@ -49,8 +49,13 @@ __global__ __launch_bounds__(kBoxThreads) void k_bbox_partial(const float *__res
     }
 }
 
+// Reduce the block partials.  fixed == 0: the cube of side = largest
+// extent at the minimum corner.  fixed == 1: the caller's box (flo, fside),
+// and kStOutside is latched when on some axis a particle lies below flo or
+// has fl32(x - flo) > fside (the difference the keys quantise).
 __global__ __launch_bounds__(64) void k_bbox_final(const float *__restrict__ part, uint32_t nb,
-                                                   float *box) {
+                                                   float *box, int fixed, float flo0, float flo1,
+                                                   float flo2, float fside, uint32_t *status) {
     float lo0 = INFINITY, lo1 = INFINITY, lo2 = INFINITY;
     float hi0 = -INFINITY, hi1 = -INFINITY, hi2 = -INFINITY;
     for (uint32_t b = threadIdx.x; b < nb; b += 64) {
@@ -61,6 +66,15 @@ __global__ __launch_bounds__(64) void k_bbox_final(const float *__restrict__ par
     lo0 = wave_min(lo0); lo1 = wave_min(lo1); lo2 = wave_min(lo2);
     hi0 = wave_max(hi0); hi1 = wave_max(hi1); hi2 = wave_max(hi2);
     if (threadIdx.x == 0) {
+        if (fixed) {
+            bool out = lo0 < flo0 || lo1 < flo1 || lo2 < flo2 || hi0 - flo0 > fside ||
+                       hi1 - flo1 > fside || hi2 - flo2 > fside;
+            if (out) atomicOr(status, kStOutside);
+            box[0] = flo0; box[1] = flo1; box[2] = flo2;
+            box[3] = fside;
+            box[4] = (float)(2097152.0 / (double)fside);
+            return;
+        }
         float side = 0.f, e;
         e = hi0 - lo0; if (e > side) side = e;
         e = hi1 - lo1; if (e > side) side = e;
@@ -79,7 +93,8 @@ void launch_bbox(bh_ctx *c, const State &s, uint32_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_bbox_partial, dim3(nb), dim3(kBoxThreads), 0, st, s.x, s.y, s.z, n,
                        c->box_part, c->status);
     hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, st, (const float *)c->box_part, nb,
-                       c->box);
+                       c->box, c->fixed_box ? 1 : 0, c->box_lo[0], c->box_lo[1], c->box_lo[2],
+                       c->box_side, c->status);
 }
 
 // 21 bits -> every third bit of a 63-bit word
@@ -96,6 +111,7 @@ __device__ __forceinline__ uint64_t spread3(uint32_t v) {
 __device__ __forceinline__ uint32_t quantise(float v, float lo, float scale) {
     float t = v - lo;
     float u = t * scale;
+    if (!(u > 0.f)) return 0u;  // below a caller-given box: the first cell
     uint32_t q = (uint32_t)u;
     return q > 0x1fffffu ? 0x1fffffu : q;
 }

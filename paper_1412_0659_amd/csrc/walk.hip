@@ -14,7 +14,9 @@
 namespace bh {
 
 struct WalkArgs {
-    const float4 *xyzm;                  // sorted positions + mass
+    const float4 *xyzm;                  // targets: sorted positions + mass
+    const float4 *sxyzm;                 // particle sources of the walked tree (= xyzm
+                                         // unless the tree is another context's)
     const float4 *wA;                    // com, r_open^2
     const uint2 *wN;                     // (first, n | leaf bit)
     const float4 *P0, *P1, *P2;          // particle-cell records
@@ -24,6 +26,8 @@ struct WalkArgs {
     uint32_t *npp, *npc, *status;
     float eps2;
     uint32_t ring;  // ring entries in use: kRing, or 128 to exercise the spill path
+    uint32_t remote;  // 1: the walked tree is another domain's (no self pair)
+    uint32_t accum;   // 1: add to acc, npp, npc instead of overwriting them
 };
 
 __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
@@ -361,7 +365,7 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
     };
     auto flush_pp = [&](uint32_t n) {
         put_null();
-        float4 r0 = a.xyzm[L.T.ppidx[lane < n ? lane : 0u]];
+        float4 r0 = a.sxyzm[L.T.ppidx[lane < n ? lane : 0u]];
         for (uint32_t base = 0; base < n; base += kChunk) {
             const uint32_t m = n - base < (uint32_t)kChunk ? n - base : (uint32_t)kChunk;
             __syncthreads();
@@ -369,7 +373,7 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
             __syncthreads();
             if (base + kChunk < n) {
                 const uint32_t q = base + kChunk + lane;
-                r0 = a.xyzm[L.T.ppidx[q < n ? q : base + kChunk]];
+                r0 = a.sxyzm[L.T.ppidx[q < n ? q : base + kChunk]];
             }
             eval_chunk<false, kEps0>(p1, m, L, a.eps2);
             if (two) eval_chunk<false, kEps0>(p2, m, L, a.eps2);
@@ -402,12 +406,16 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
     }
     if (own) {
         // the self pair was evaluated with r^2 = eps^2; take its potential out
-        if (!kEps0) res.w += me.w * rsq(a.eps2);
+        if (!kEps0 && !a.remote) res.w += me.w * rsq(a.eps2);
+        if (a.accum) {
+            const float4 o = a.acc[gb + lane];
+            res.x = o.x + res.x; res.y = o.y + res.y; res.z = o.z + res.z; res.w = o.w + res.w;
+        }
         a.acc[gb + lane] = res;
     }
     if (lane == 0) {
-        a.npp[g] = cnt_pp;
-        a.npc[g] = cnt_pc;
+        a.npp[g] = (a.accum ? a.npp[g] : 0u) + cnt_pp;
+        a.npc[g] = (a.accum ? a.npc[g] : 0u) + cnt_pc;
     }
     __syncthreads();
 }
@@ -441,20 +449,27 @@ int walk_blocks_per_cu() {
     return nb;
 }
 
-void launch_walk(bh_ctx *c, float eps, hipStream_t st) {
+void launch_walk_view(bh_ctx *c, const SrcView &v, float eps, bool remote, bool accum,
+                      hipStream_t st) {
     WalkArgs a;
     a.xyzm = c->xyzm;
-    a.wA = c->cells.wA; a.wN = c->cells.wN;
-    a.P0 = c->cells.P0; a.P1 = c->cells.P1; a.P2 = c->cells.P2;
+    a.sxyzm = v.xyzm;
+    a.wA = v.wA; a.wN = v.wN;
+    a.P0 = v.P0; a.P1 = v.P1; a.P2 = v.P2;
     a.gbeg = c->groups.begin; a.ngroups = c->groups.count_dev;
     a.work = c->work; a.spill = c->spill;
     a.acc = c->acc; a.gbox = c->groups.box;
     a.npp = c->groups.npp; a.npc = c->groups.npc; a.status = c->status;
     a.eps2 = eps * eps;
     a.ring = c->walk_small_stack ? 128u : (uint32_t)kRing;
+    a.remote = remote ? 1u : 0u;
+    a.accum = accum ? 1u : 0u;
     hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(64), 0, st, c->work);
-    (void)hipEventRecord(c->ev[4], st);
-    c->ev_rec[4] = true;
+    const bool own = !remote && !accum;  // the timed walk of the context's own tree
+    if (own) {
+        (void)hipEventRecord(c->ev[4], st);
+        c->ev_rec[4] = true;
+    }
     const bool f16 = c->p.far_fp16 != 0;
     if (eps == 0.f && f16)
         hipLaunchKernelGGL((k_walk<true, true>), dim3(c->walk_grid), dim3(64), 0, st, a);
@@ -464,8 +479,22 @@ void launch_walk(bh_ctx *c, float eps, hipStream_t st) {
         hipLaunchKernelGGL((k_walk<false, true>), dim3(c->walk_grid), dim3(64), 0, st, a);
     else
         hipLaunchKernelGGL((k_walk<false, false>), dim3(c->walk_grid), dim3(64), 0, st, a);
-    (void)hipEventRecord(c->ev[5], st);
-    c->ev_rec[5] = true;
+    if (own) {
+        (void)hipEventRecord(c->ev[5], st);
+        c->ev_rec[5] = true;
+    }
+}
+
+SrcView own_view(const bh_ctx *c) {
+    SrcView v;
+    v.wA = c->cells.wA; v.wN = c->cells.wN;
+    v.P0 = c->cells.P0; v.P1 = c->cells.P1; v.P2 = c->cells.P2;
+    v.xyzm = c->xyzm;
+    return v;
+}
+
+void launch_walk(bh_ctx *c, float eps, hipStream_t st) {
+    launch_walk_view(c, own_view(c), eps, false, false, st);
 }
 
 }  // namespace bh

@@ -1,0 +1,342 @@
+"""Several spatial domains on one GPU (Sec. III.B) against the oracle: trees
+keyed in the global box (bit-exact), the flop-weighted cut of the curve
+(bit-exact), the particle exchange (bit-exact), boundary trees and their
+boxes (bit-exact), the cells of each local essential tree (bit-exact sets),
+remote-tree walks and the merged LET walk (forces to the walk tolerance,
+interaction counts exact, and the LET walk bit-identical to walking the
+full remote tree), and the whole multi-domain force."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_tree_equal, gpu_force, gpu_tree, rel_err, to_dev
+from oracle import let as LT
+from workloads import ics
+
+pytestmark = pytest.mark.gpu
+
+MED_TOL, P99_TOL = 1e-5, 1e-4
+
+
+def _disk(n, seed=3):
+    s = ics.disk_halo_scaled(n, seed=seed)
+    return s.pos.astype(np.float32), s.mass.astype(np.float32)
+
+
+def _clusters(n_per, seed=7):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for c in ([0, 0, 0], [40, 0, 0], [0, 40, 0], [0, 0, 40]):
+        v = rng.normal(size=(n_per, 3))
+        r = rng.random(n_per) ** (1.0 / 3.0)
+        parts.append(v / np.linalg.norm(v, axis=1, keepdims=True) * r[:, None] + c)
+    pos = np.concatenate(parts).astype(np.float32)
+    return pos, np.full(pos.shape[0], 1.0 / pos.shape[0], np.float32)
+
+
+def _oracle_domains(oracle, pos, mass, p, curve, theta, eps, cap=1.3):
+    g = oracle.build_tree(pos, mass, curve=curve)
+    _, _, npp, npc = oracle.walk(g, theta, eps)
+    cuts = LT.decompose(LT.particle_cost(g.n, g.gbeg, g.gcnt, npp, npc), p, cap)
+    box = (g.lo, g.side)
+    doms = [g.perm[cuts[d]:cuts[d + 1]] for d in range(p)]
+    return g, cuts, box, doms
+
+
+def _gpu_domain_trees(pos, mass, doms, box, curve="morton", max_cells=None):
+    from paper_1412_0659_amd import Tree
+    trees = []
+    for ix in doms:
+        t = Tree(len(ix), curve=curve)
+        t.set_box(box[0], box[1])
+        t.build(to_dev(pos[ix]), to_dev(mass[ix]))
+        if max_cells:
+            t.boundary(max_cells)
+        t.sync()
+        trees.append(t)
+    return trees
+
+
+def _norm_err(a, ref, scale):
+    return np.linalg.norm(np.asarray(a) - ref, axis=-1) / np.linalg.norm(scale, axis=-1)
+
+
+# --- trees in the global box ---------------------------------------------------------
+
+@pytest.mark.parametrize("curve", ["morton", "ph"])
+def test_fixed_box_tree_bit_exact(oracle, curve):
+    pos, mass = _disk(20000)
+    lo = pos.min(0) - np.float32(3.0)
+    side = float((pos.max(0) - pos.min(0)).max()) * 1.7
+    box = (lo, side)
+    from paper_1412_0659_amd import Tree
+    t = Tree(pos.shape[0], curve=curve)
+    t.set_box(lo, side)
+    t.build(to_dev(pos), to_dev(mass))
+    t.sync()
+    ot = oracle.build_tree(pos, mass, curve=curve, box=box)
+    assert_tree_equal(t, ot)
+    assert np.array_equal(t.export("mom_M"), ot.mom["M"])
+    assert np.array_equal(t.export("mom_Q"), ot.mom["Q"])
+    assert np.array_equal(t.export("cell_size")[:, 1], ot.mom["deltaf"])
+    # back to the own box
+    t.set_box(None)
+    t.build(to_dev(pos), to_dev(mass))
+    t.sync()
+    assert_tree_equal(t, oracle.build_tree(pos, mass, curve=curve))
+
+
+def test_particle_outside_the_box_is_an_error():
+    from paper_1412_0659_amd import BhError, Tree
+    pos, mass = _disk(2000)
+    t = Tree(pos.shape[0])
+    t.set_box(pos.min(0), float((pos.max(0) - pos.min(0)).max()) * 0.5)
+    t.build(to_dev(pos), to_dev(mass))
+    with pytest.raises(BhError) as e:
+        t.sync()
+    assert e.value.code == -1 and "box" in str(e.value)
+    with pytest.raises(BhError):
+        t.set_box([0, 0, 0], 0.0)
+    with pytest.raises(BhError):
+        t.set_box([np.nan, 0, 0], 1.0)
+
+
+# --- the cut and the particle exchange ---------------------------------------------
+
+@pytest.mark.parametrize("curve,p,cap", [("morton", 4, 1.3), ("ph", 7, 1.3), ("morton", 16, 1.05),
+                                         ("ph", 1, 1.3), ("morton", 3, 1.0)])
+def test_decompose_and_extract_bit_exact(oracle, curve, p, cap):
+    pos, mass = _disk(30000)
+    theta, eps = 0.4, 0.01
+    g, cuts, box, doms = _oracle_domains(oracle, pos, mass, p, curve, theta, eps, cap)
+    t = gpu_tree(pos, mass, curve=curve)
+    gpu_force(t, theta, eps)
+    gcuts = t.decompose(p, cap)
+    print(f"  {curve} p={p} cap={cap}: cuts {gcuts.tolist()}", flush=True)
+    assert np.array_equal(gcuts, cuts)
+    C = int(np.floor(float(np.float32(cap)) * pos.shape[0] / p))
+    assert np.all(np.diff(gcuts) <= C)
+    for d in range(p):
+        dpos, dvel, dmass, dids = t.extract(int(gcuts[d]), int(gcuts[d + 1]))
+        assert np.array_equal(dids.cpu().numpy().astype(np.int64), doms[d])
+        assert np.array_equal(dpos.cpu().numpy(), pos[doms[d]])
+        assert np.array_equal(dmass.cpu().numpy(), mass[doms[d]])
+
+
+def test_decompose_errors():
+    from paper_1412_0659_amd import BhError
+    pos, mass = _disk(3000)
+    t = gpu_tree(pos, mass)
+    with pytest.raises(BhError):
+        t.decompose(4)            # no walk yet
+    gpu_force(t, 0.5, 0.01)
+    for p, cap in ((0, 1.3), (4, 0.5), (7, 1.0), (5000, 1.3)):
+        with pytest.raises(BhError):
+            t.decompose(p, cap)
+    from paper_1412_0659_amd import bh_domain_extract
+    for lo, hi in ((10, 5), (-1, 5), (0, 3001)):
+        with pytest.raises(BhError):
+            bh_domain_extract(t.ctx, lo, hi)
+
+
+# --- boundary trees, remote walks, LETs --------------------------------------------
+
+@pytest.mark.parametrize("curve,max_cells", [("morton", 128), ("ph", 512), ("morton", 1)])
+def test_boundary_bit_exact(oracle, curve, max_cells):
+    pos, mass = _disk(30000)
+    g, cuts, box, doms = _oracle_domains(oracle, pos, mass, 4, curve, 0.4, 0.01)
+    trees = _gpu_domain_trees(pos, mass, doms, box, curve)
+    for ix, t in zip(doms, trees):
+        ot = oracle.build_tree(pos[ix], mass[ix], curve=curve, box=box)
+        assert_tree_equal(t, ot)
+        L, inb, term = LT.boundary(ot, max_cells)
+        lev, nterm = t.boundary(max_cells)
+        assert lev == L and nterm == int(term.sum())
+        flag = t.export("boundary_flag")
+        assert np.array_equal((flag & 1).astype(bool), inb)
+        assert np.array_equal((flag & 2).astype(bool), term)
+        ids, bc, bh = LT.boundary_boxes(ot, term, box)
+        assert np.array_equal(t.export("boundary_cells").astype(np.int64), ids)
+        b = t.export("boundary_box")
+        assert np.array_equal(b[:, 0:3], bc) and np.array_equal(b[:, 4:7], bh)
+
+
+@pytest.mark.parametrize("curve", ["morton", "ph"])
+def test_remote_walk_and_let(oracle, curve):
+    pos, mass = _disk(40000)
+    theta, eps = 0.5, 0.01
+    g, cuts, box, doms = _oracle_domains(oracle, pos, mass, 4, curve, theta, eps)
+    trees = _gpu_domain_trees(pos, mass, doms, box, curve, max_cells=128)
+    otrees = [oracle.build_tree(pos[ix], mass[ix], curve=curve, box=box) for ix in doms]
+    obnd = [LT.boundary(ot, 128) for ot in otrees]
+    import torch
+    for a in (0, 2):
+        ta, ota = trees[a], otrees[a]
+        own, ownp, onpp, onpc = oracle.walk(ota, theta, eps)
+        tot_acc, tot_pot = own.copy(), ownp.copy()
+        rem = []
+        for b in range(4):
+            if b == a:
+                continue
+            r = LT.walk_remote(ota, otrees[b], theta, eps)
+            tot_acc += r[0]
+            tot_pot += r[1]
+            rem.append(r)
+        # remote full-tree walks through tree_force_add, one source at a time
+        k = 0
+        for b in range(4):
+            if b == a:
+                continue
+            acc = torch.zeros((ta.n, 3), dtype=torch.float32, device="cuda")
+            pot = torch.zeros((ta.n,), dtype=torch.float32, device="cuda")
+            ta.force_add(trees[b], theta, eps, acc, pot)
+            ta.sync()
+            assert np.array_equal(ta.export("group_npp").astype(np.int64), rem[k][2])
+            assert np.array_equal(ta.export("group_npc").astype(np.int64), rem[k][3])
+            ea = _norm_err(acc.cpu().numpy(), rem[k][0], tot_acc)
+            ep = np.abs(pot.cpu().numpy() - rem[k][1]) / np.abs(tot_pot)
+            print(f"  {curve} {a}<-{b}: acc med {np.median(ea):.2e} p99 "
+                  f"{np.percentile(ea, 99):.2e}", flush=True)
+            assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
+            assert np.median(ep) <= MED_TOL and np.percentile(ep, 99) <= P99_TOL
+            k += 1
+        # the LET cells against the oracle's reached cells
+        srcs = [trees[b] for b in range(4) if b != a]
+        info = ta.let_build(srcs, theta)
+        origin = ta.export("let_origin").astype(np.int64)
+        _, bc, bh = LT.boundary_boxes(ota, obnd[a][2], box)
+        for k, b in enumerate([b for b in range(4) if b != a]):
+            vis, opn, ins = LT.let_mark(otrees[b], theta, bc, bh, obnd[b][2])
+            keep = obnd[b][1] if not ins else vis
+            got = np.sort(origin[origin[:, 0] == k, 1])
+            assert np.array_equal(got, np.nonzero(keep)[0]), (a, b)
+            assert info[k, 0] == (0 if ins else 1) and info[k, 1] == int(keep.sum())
+            np_ = 0 if not ins else int(otrees[b].cells["count"][opn & (otrees[b].cells["nchild"] == 0)].sum())
+            assert info[k, 2] == np_
+        # own + LET walk against the oracle's own + remote walks
+        acc, pot = ta.force_let(theta, eps)
+        ta.sync()
+        ea = rel_err(acc.cpu().numpy(), tot_acc)
+        ep = rel_err(pot.cpu().numpy(), tot_pot)
+        print(f"  {curve} domain {a} own+LET: acc med {np.median(ea):.2e} p99 "
+              f"{np.percentile(ea, 99):.2e}", flush=True)
+        assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
+        assert np.median(ep) <= MED_TOL and np.percentile(ep, 99) <= P99_TOL
+        npp = onpp + sum(r[2] for r in rem)
+        npc = onpc + sum(r[3] for r in rem)
+        assert np.array_equal(ta.export("group_npp").astype(np.int64), npp)
+        assert np.array_equal(ta.export("group_npc").astype(np.int64), npc)
+
+
+@pytest.mark.parametrize("f16", [False, True])
+def test_let_walk_bit_identical_to_full_remote_walk(oracle, f16):
+    """One source: own walk + LET walk equals, bit for bit, the own walk plus
+    the walk of the source's full tree (the LET holds every cell and
+    particle the groups reach, in the same order)."""
+    import torch
+    from paper_1412_0659_amd import Tree
+    pos, mass = _disk(30000)
+    theta, eps = 0.45, 0.01
+    g, cuts, box, doms = _oracle_domains(oracle, pos, mass, 3, "morton", theta, eps)
+    trees = []
+    for ix in doms:
+        t = Tree(len(ix), far_fp16=f16)
+        t.set_box(*box)
+        t.build(to_dev(pos[ix]), to_dev(mass[ix]))
+        t.boundary(64)
+        trees.append(t)
+    for a, b in ((0, 1), (1, 2), (2, 0)):
+        ta, tb = trees[a], trees[b]
+        own_acc, own_pot = ta.force(theta, eps)
+        radd = torch.zeros_like(own_acc)
+        rpot = torch.zeros_like(own_pot)
+        ta.force_add(tb, theta, eps, radd, rpot)
+        ta.let_build([tb], theta)
+        acc, pot = ta.force_let(theta, eps)
+        ta.sync()
+        assert torch.equal(acc, own_acc + radd) and torch.equal(pot, own_pot + rpot), (a, b)
+
+
+def test_far_clusters_use_boundary_trees(oracle):
+    pos, mass = _clusters(3000)
+    theta, eps = 0.5, 0.01
+    g = oracle.build_tree(pos, mass)
+    box = (g.lo, g.side)
+    doms = [np.arange(k * 3000, (k + 1) * 3000) for k in range(4)]
+    trees = _gpu_domain_trees(pos, mass, doms, box, max_cells=64)
+    dacc, dpot = oracle.direct(pos, mass, eps)
+    for a in range(4):
+        info = trees[a].let_build([trees[b] for b in range(4) if b != a], theta)
+        assert np.all(info[:, 0] == 1) and np.all(info[:, 2] == 0)
+        acc, pot = trees[a].force_let(theta, eps)
+        trees[a].sync()
+        ea = rel_err(acc.cpu().numpy(), dacc[doms[a]])
+        assert np.median(ea) < 2e-3 and np.percentile(ea, 99) < 2e-2
+
+
+@pytest.mark.parametrize("curve,p", [("morton", 4), ("ph", 10)])
+def test_domains_total_force(oracle, curve, p):
+    from paper_1412_0659_amd import Domains
+    pos, mass = _disk(40000)
+    theta, eps = 0.4, 0.01
+    d = Domains(to_dev(pos), to_dev(mass), p, theta, eps, max_boundary=256, curve=curve)
+    info = d.build_lets()
+    acc, pot = d.forces()
+    import torch
+    torch.cuda.synchronize()
+    g, cuts, box, doms = _oracle_domains(oracle, pos, mass, p, curve, theta, eps)
+    assert np.array_equal(d.cuts, cuts)
+    oacc, opot, _ = LT.domain_forces(pos, mass, doms, box, theta, eps, curve)
+    ea = rel_err(acc.cpu().numpy(), oacc)
+    ep = rel_err(pot.cpu().numpy(), opot)
+    nsuff = sum(int(i[:, 0].sum()) for i in info)
+    print(f"  {curve} p={p}: acc med {np.median(ea):.2e} p99 {np.percentile(ea, 99):.2e}; "
+          f"boundary trees used {nsuff} of {p * (p - 1)}", flush=True)
+    assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
+    assert np.median(ep) <= MED_TOL and np.percentile(ep, 99) <= P99_TOL
+    # against one tree over all particles: the opening-angle error only
+    t = gpu_tree(pos, mass, curve=curve)
+    acc1, _ = gpu_force(t, theta, eps)
+    dacc, _ = oracle.direct(pos, mass, eps, targets=np.arange(0, 40000, 97))
+    e1 = rel_err(acc.cpu().numpy()[::97], dacc)
+    e0 = rel_err(acc1[::97], dacc)
+    assert np.median(e1) < 2 * np.median(e0) + 1e-6
+    d.close()
+
+
+def test_let_errors():
+    from paper_1412_0659_amd import BhError, Tree
+    pos, mass = _disk(4000)
+    box = (pos.min(0), float((pos.max(0) - pos.min(0)).max()))
+    a, b = Tree(2000), Tree(2000)
+    for t, sl in ((a, slice(0, 2000)), (b, slice(2000, 4000))):
+        t.set_box(*box)
+        t.build(to_dev(pos[sl]), to_dev(mass[sl]))
+    with pytest.raises(BhError):
+        a.let_build([b], 0.5)         # no boundary trees yet
+    a.boundary(64)
+    with pytest.raises(BhError):
+        a.let_build([b], 0.5)         # the source has none either
+    b.boundary(64)
+    with pytest.raises(BhError):
+        a.force_let(0.5, 0.01)        # no LET yet
+    with pytest.raises(BhError):
+        a.let_build([a], 0.5)         # itself
+    with pytest.raises(BhError):
+        a.let_build([b, b], 0.5)      # twice
+    a.let_build([b], 0.5)
+    with pytest.raises(BhError):
+        a.force_let(0.6, 0.01)        # another theta
+    with pytest.raises(BhError):
+        a.force_add(a, 0.5, 0.01, None, None)
+    c = Tree(2000)
+    c.build(to_dev(pos[:2000]), to_dev(mass[:2000]))
+    c.boundary(64)
+    with pytest.raises(BhError):
+        a.let_build([c], 0.5)         # not in the shared box
+    a.let_build([], 0.5)              # a single domain: empty LET
+    acc, pot = a.force_let(0.5, 0.01)
+    a.sync()
+    acc0, pot0 = a.force(0.5, 0.01)
+    a.sync()
+    import torch
+    assert torch.equal(acc, acc0) and torch.equal(pot, pot0)
