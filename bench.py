@@ -256,6 +256,104 @@ def adjoint(name="disk_halo_1m_adjoint", log=print):
             "ms_per_step_backward": 1e3 * bwd / w["steps"], "grad_finite": finite}
 
 
+def domains(name="disk_halo_13m", ps=(2, 4, 8, 16), curve="ph", max_boundary=4096, reps=3,
+            log=print):
+    """The force evaluation split into p spatial domains on the one device
+    (Sec. III.B): flop-weighted cuts, per-domain trees in the global box,
+    boundary trees, merged local essential trees, own + LET walks; against
+    one tree over all particles."""
+    import numpy as np
+    import torch
+
+    import paper_1412_0659_amd as bh
+    from workloads import ics
+    w = ics.WORKLOADS[name]
+    theta, eps = w["theta"], w["eps"]
+    snap = ics.make(name)
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(snap.pos).to(dev)
+    mass = torch.from_numpy(snap.mass).to(dev)
+    one = bh.Tree(snap.n, curve=curve)
+    one.build(pos, mass)
+    ms1, acc1, _, st1 = _timed_force(one, theta, eps, reps)
+    inter1 = st1["n_pp"] + st1["n_pc"]
+    a1 = torch.empty((snap.n, 3), dtype=torch.float32, device=dev)
+    p1 = torch.empty((snap.n,), dtype=torch.float32, device=dev)
+    calls = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        one.force(theta, eps, a1, p1)
+        e1.record()
+        torch.cuda.synchronize()
+        calls.append(e0.elapsed_time(e1))
+    call1 = float(np.median(calls))
+    one.close()
+    sample = np.arange(0, snap.n, 211)
+    ref = acc1[sample]
+    rows = []
+    for p in ps:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d = bh.Domains(pos, mass, p, theta, eps, max_boundary=max_boundary, curve=curve)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        info = d.build_lets()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        acc, pot = d.forces()
+        times, per_dom, conc = [], [], []
+        for _ in range(reps):
+            # one stream, domain after domain: per-domain times
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(d.trees) + 1)]
+            ev[0].record()
+            for k, (t, ids) in enumerate(zip(d.trees, d.ids)):
+                t.force_let(theta, eps, rows=ids, acc=acc, pot=pot)
+                ev[k + 1].record()
+            torch.cuda.synchronize()
+            times.append(ev[0].elapsed_time(ev[-1]))
+            per_dom.append([ev[k].elapsed_time(ev[k + 1]) for k in range(len(d.trees))])
+            # the domains on four streams at once
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            d.forces(acc=acc, pot=pot)
+            e1.record()
+            torch.cuda.synchronize()
+            conc.append(e0.elapsed_time(e1))
+        ms_serial = float(np.median(times))
+        ms = float(np.median(conc))
+        dom_ms = np.median(np.asarray(per_dom), axis=0)
+        inter = 0
+        for t in d.trees:
+            st = t.stats()
+            inter += st["n_pp"] + st["n_pc"]
+        err = _rel(acc.double().cpu().numpy()[sample], ref)
+        allinfo = np.concatenate([i for i in info if len(i)]) if p > 1 else np.zeros((0, 3))
+        let_cells = int(allinfo[:, 1].sum()) if len(allinfo) else 0
+        let_parts = int(allinfo[:, 2].sum()) if len(allinfo) else 0
+        row = {"p": p, "cuts_sizes": np.diff(d.cuts).tolist(), "setup_s": t1 - t0,
+               "let_build_s": t2 - t1, "force_ms": ms, "force_ms_one_stream": ms_serial,
+               "domain_ms_max": float(dom_ms.max()),
+               "domain_ms_min": float(dom_ms.min()),
+               "interactions": int(inter), "interactions_over_one_tree": inter / inter1,
+               "interactions_per_s": inter / (ms * 1e-3),
+               "tflops": paper_flops(sum(t.stats()["n_pp"] for t in d.trees),
+                                     sum(t.stats()["n_pc"] for t in d.trees)) / (ms * 1e-3) / 1e12,
+               "boundary_sufficed": int(allinfo[:, 0].sum()) if len(allinfo) else 0,
+               "pairs": p * (p - 1), "let_cells": let_cells, "let_particles": let_parts,
+               "acc_rel_diff_vs_one_tree_median": float(np.median(err)),
+               "acc_rel_diff_vs_one_tree_p99": float(np.percentile(err, 99))}
+        log(f"[bench] domains p={p}: force {ms:.1f} ms on 4 streams, {ms_serial:.1f} ms on "
+            f"one (one tree {call1:.1f}), "
+            f"interactions x{inter / inter1:.3f}, LET build {t2 - t1:.2f} s, "
+            f"boundary trees {row['boundary_sufficed']}/{row['pairs']}")
+        rows.append(row)
+        d.close()
+    return {"workload": name, "n": snap.n, "theta": theta, "eps": eps, "curve": curve,
+            "max_boundary": max_boundary, "one_tree_walk_ms": ms1, "one_tree_force_ms": call1,
+            "one_tree_interactions": int(inter1), "rows": rows}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,6 +369,9 @@ def main(argv=None):
                     help="only run the precision form's table (4M disk + halo, theta 0.3/0.4/0.6)")
     ap.add_argument("--param-sweep", action="store_true",
                     help="only run the walk cost sweep over theta and (nleaf, ncrit) at 4M")
+    ap.add_argument("--domains", type=str, default=None,
+                    help="comma-separated domain counts: time the multi-domain force "
+                         "(own + local-essential-tree walks) instead")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the differentiation workload and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -310,6 +411,10 @@ def main(argv=None):
         return 0
     if args.param_sweep:
         print(json.dumps(param_sweep(log=log)))
+        return 0
+    if args.domains:
+        ps = tuple(int(v) for v in args.domains.split(","))
+        print(json.dumps(domains(args.workload, ps, args.curve, log=log)))
         return 0
 
     w = ics.WORKLOADS[args.workload]

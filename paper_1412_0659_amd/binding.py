@@ -517,11 +517,11 @@ class Tree:
             sizes.insert(0, (sizes[0] + 7) // 8)
         return sum(sizes[:-1])
 
-    def force_let(self, theta, eps, rows=None, acc=None, pot=None):
+    def force_let(self, theta, eps, rows=None, acc=None, pot=None, stream=None):
         import torch
         if acc is None:
             acc = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
         if pot is None:
             pot = torch.empty((self.n,), dtype=torch.float32, device="cuda")
-        tree_force_let(self.ctx, theta, eps, rows, acc, pot)
+        tree_force_let(self.ctx, theta, eps, rows, acc, pot, stream)
         return acc, pot

@@ -59,7 +59,7 @@ void free_all(bh_ctx *c) {
     f(g.flag); f(g.scan); f(g.begin); f(g.count_dev); f(g.box); f(g.npp); f(g.npc);
     f(c->lcell); f(c->gsrc); f(c->usort); f(c->leafof); f(c->cic); f(c->inv); f(c->diag);
     Boundary &b = c->bnd;
-    f(b.flag); f(b.scan); f(b.ids); f(b.box); f(b.lvl); f(b.part);
+    f(b.flag); f(b.scan); f(b.ids); f(b.box); f(b.cmin); f(b.cmax); f(b.lvl); f(b.part);
     Let &t = c->let;
     f(t.wA); f(t.P0); f(t.P1); f(t.P2); f(t.xyzm); f(t.wN); f(t.origin);
     f(t.cmark); f(t.cscan); f(t.pmark); f(t.pscan); f(t.spart); f(t.word);
@@ -673,13 +673,19 @@ int bh_boundary(bh_ctx *c, int32_t max_cells, int32_t *level, int64_t *nterm, hi
     Boundary &b = c->bnd;
     std::string err;
     const int64_t cap = c->cap_cells + 1;
-    int64_t c1 = b.flag ? cap : 0, c2 = c1, c3 = c1, c4 = c1, c5 = c1, c6 = c1;
+    int64_t c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0, c8 = 0;
     const int64_t plen = scan_part_len(cap);
     if (!b.flag) {
         if (!grow(&b.flag, c1, cap, err) || !grow(&b.scan, c2, cap, err) ||
             !grow(&b.ids, c3, cap, err) || !grow(&b.box, c4, 2 * cap, err) ||
-            !grow(&b.lvl, c5, kLevels, err) || !grow(&b.part, c6, plen, err))
+            !grow(&b.cmin, c7, cap, err) || !grow(&b.cmax, c8, cap, err) ||
+            !grow(&b.lvl, c5, kLevels, err) || !grow(&b.part, c6, plen, err)) {
+            Boundary z{};
+            auto f = [](void *q) { if (q) (void)hipFree(q); };
+            f(b.flag); f(b.scan); f(b.ids); f(b.box); f(b.cmin); f(b.cmax); f(b.lvl); f(b.part);
+            b = z;
             return fail(c, BH_ENOMEM, err);
+        }
     }
     b.valid = false;
     launch_bnd_flags(c, s);

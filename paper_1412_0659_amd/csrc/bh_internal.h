@@ -75,6 +75,7 @@ struct Boundary {
     uint32_t *scan = nullptr;  // [cap_cells + 1] exclusive scan of the terminal bits
     uint32_t *ids = nullptr;   // [cap_cells] terminal cells in cell order
     float4 *box = nullptr;     // [2 cap_cells] centre, half size (widened) of each
+    float4 *cmin = nullptr, *cmax = nullptr;  // [cap_cells] FP32 particle box of every cell
     uint32_t *lvl = nullptr;   // [kLevels] boundary cells per level
     uint32_t *part = nullptr;  // scan partials
 };

@@ -41,10 +41,65 @@ uint32_t cell_count(const bh_ctx *c, hipStream_t st) {
 __global__ __launch_bounds__(256) void k_bnd_flags(Cells c, uint32_t ncrit, uint32_t *flag,
                                                    uint32_t *lvl) {
     const uint32_t nc = c.ls[kLevels];
+    const uint32_t lane = threadIdx.x & 63u;
+    // every thread of a wave runs the same trips, so the counts can be
+    // combined across the wave (cells are level-ordered: most waves see one level)
+    for (uint32_t base = blockIdx.x * 256 + (threadIdx.x & ~63u); base < nc;
+         base += gridDim.x * 256) {
+        const uint32_t i = base + lane;
+        bool inb = false;
+        uint32_t lev = kLevels;
+        if (i < nc) {
+            inb = i == 0u || c.count[c.parent[i]] > ncrit;
+            flag[i] = inb ? 1u : 0u;
+            lev = c.level[i];
+        }
+        const uint32_t lev0 = shfl(lev, 0);
+        if (ballot(lev != lev0 && i < nc) == 0ull) {
+            const uint32_t k = (uint32_t)__popcll(ballot(inb));
+            if (lane == 0 && k) atomicAdd(&lvl[lev0], k);
+        } else if (inb) {
+            atomicAdd(&lvl[lev], 1u);
+        }
+    }
+}
+
+// FP32 bounding box of every cell's particles, from the deepest level up:
+// a leaf over its particles, an internal cell over its children (min and
+// max are exact, so this equals the box over the particles)
+__global__ __launch_bounds__(256) void k_cbox_leaf(Cells c, const float4 *__restrict__ xyzm,
+                                                   float4 *__restrict__ cmin,
+                                                   float4 *__restrict__ cmax) {
+    const uint32_t nc = c.ls[kLevels];
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) {
-        const bool inb = i == 0u || c.count[c.parent[i]] > ncrit;
-        flag[i] = inb ? 1u : 0u;
-        if (inb) atomicAdd(&lvl[c.level[i]], 1u);
+        if (c.nchild[i] != 0u) continue;
+        const uint32_t b = c.begin[i], e = b + c.count[i];
+        float4 mn = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+        float4 mx = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
+        for (uint32_t j = b; j < e; ++j) {
+            const float4 p = xyzm[j];
+            mn.x = fminf(mn.x, p.x); mn.y = fminf(mn.y, p.y); mn.z = fminf(mn.z, p.z);
+            mx.x = fmaxf(mx.x, p.x); mx.y = fmaxf(mx.y, p.y); mx.z = fmaxf(mx.z, p.z);
+        }
+        cmin[i] = mn;
+        cmax[i] = mx;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cbox_up(Cells c, int l, float4 *cmin, float4 *cmax) {
+    const uint32_t first = c.ls[l], last = c.ls[l + 1];
+    for (uint32_t i = first + blockIdx.x * 256 + threadIdx.x; i < last; i += gridDim.x * 256) {
+        const uint32_t nch = c.nchild[i];
+        if (nch == 0u) continue;
+        const uint32_t k0 = c.child0[i];
+        float4 mn = cmin[k0], mx = cmax[k0];
+        for (uint32_t k = k0 + 1; k < k0 + nch; ++k) {
+            const float4 a = cmin[k], b = cmax[k];
+            mn.x = fminf(mn.x, a.x); mn.y = fminf(mn.y, a.y); mn.z = fminf(mn.z, a.z);
+            mx.x = fmaxf(mx.x, b.x); mx.y = fmaxf(mx.y, b.y); mx.z = fmaxf(mx.z, b.z);
+        }
+        cmin[i] = mn;
+        cmax[i] = mx;
     }
 }
 
@@ -73,32 +128,20 @@ __global__ __launch_bounds__(256) void k_bnd_ids(const uint32_t *__restrict__ fl
         if (flag[i] & 2u) ids[tscan[i]] = i;
 }
 
-// one wave per terminal cell: tight FP32 box of its particles,
-// centre (min + max) / 2, half size (max - min) / 2 + margin
-__global__ __launch_bounds__(256) void k_bnd_box(Cells c, const uint32_t *__restrict__ ids,
-                                                 uint32_t nterm, const float4 *__restrict__ xyzm,
-                                                 float margin, float4 *__restrict__ box) {
-    const uint32_t lane = threadIdx.x & 63u;
-    for (uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6); k < nterm; k += gridDim.x * 4) {
+// tight FP32 box of each terminal cell: centre (min + max) / 2, half size
+// (max - min) / 2 + margin
+__global__ __launch_bounds__(256) void k_bnd_box(const uint32_t *__restrict__ ids, uint32_t nterm,
+                                                 const float4 *__restrict__ cmin,
+                                                 const float4 *__restrict__ cmax, float margin,
+                                                 float4 *__restrict__ box) {
+    for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < nterm; k += gridDim.x * 256) {
         const uint32_t cell = ids[k];
-        const uint32_t b = c.begin[cell], e = b + c.count[cell];
-        float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY;
-        float mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY;
-        for (uint32_t j = b + lane; j < e; j += 64u) {
-            const float4 p = xyzm[j];
-            mn0 = fminf(mn0, p.x); mx0 = fmaxf(mx0, p.x);
-            mn1 = fminf(mn1, p.y); mx1 = fmaxf(mx1, p.y);
-            mn2 = fminf(mn2, p.z); mx2 = fmaxf(mx2, p.z);
-        }
-        mn0 = wave_min(mn0); mn1 = wave_min(mn1); mn2 = wave_min(mn2);
-        mx0 = wave_max(mx0); mx1 = wave_max(mx1); mx2 = wave_max(mx2);
-        if (lane == 0) {
-            box[2 * (size_t)k] = make_float4((mn0 + mx0) * 0.5f, (mn1 + mx1) * 0.5f,
-                                             (mn2 + mx2) * 0.5f, 0.f);
-            box[2 * (size_t)k + 1] =
-                make_float4((mx0 - mn0) * 0.5f + margin, (mx1 - mn1) * 0.5f + margin,
-                            (mx2 - mn2) * 0.5f + margin, 0.f);
-        }
+        const float4 mn = cmin[cell], mx = cmax[cell];
+        box[2 * (size_t)k] = make_float4((mn.x + mx.x) * 0.5f, (mn.y + mx.y) * 0.5f,
+                                         (mn.z + mx.z) * 0.5f, 0.f);
+        box[2 * (size_t)k + 1] =
+            make_float4((mx.x - mn.x) * 0.5f + margin, (mx.y - mn.y) * 0.5f + margin,
+                        (mx.z - mn.z) * 0.5f + margin, 0.f);
     }
 }
 
@@ -114,14 +157,18 @@ void launch_bnd_terminal(bh_ctx *c, int level, hipStream_t st) {
 }
 
 void launch_bnd_boxes(bh_ctx *c, uint32_t nc, uint32_t nterm, hipStream_t st) {
-    hipLaunchKernelGGL(k_bnd_ids, dim3(kGrid), dim3(256), 0, st, (const uint32_t *)c->bnd.flag,
-                       (const uint32_t *)c->bnd.scan, nc, c->bnd.ids);
+    Boundary &b = c->bnd;
+    hipLaunchKernelGGL(k_bnd_ids, dim3(kGrid), dim3(256), 0, st, (const uint32_t *)b.flag,
+                       (const uint32_t *)b.scan, nc, b.ids);
     if (nterm == 0) return;
-    uint32_t nb = cdiv(nterm, 4);
+    hipLaunchKernelGGL(k_cbox_leaf, dim3(kGrid * 2), dim3(256), 0, st, c->cells,
+                       (const float4 *)c->xyzm, b.cmin, b.cmax);
+    for (int l = kLevels - 2; l >= 0; --l)
+        hipLaunchKernelGGL(k_cbox_up, dim3(kGrid), dim3(256), 0, st, c->cells, l, b.cmin, b.cmax);
+    uint32_t nb = cdiv(nterm, 256);
     if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_bnd_box, dim3(nb), dim3(256), 0, st, c->cells,
-                       (const uint32_t *)c->bnd.ids, nterm, (const float4 *)c->xyzm,
-                       c->bnd.margin, c->bnd.box);
+    hipLaunchKernelGGL(k_bnd_box, dim3(nb), dim3(256), 0, st, (const uint32_t *)b.ids, nterm,
+                       (const float4 *)b.cmin, (const float4 *)b.cmax, b.margin, b.box);
 }
 
 // ---- local essential tree ---------------------------------------------------

@@ -48,6 +48,7 @@ class Domains:
             self.slots.append((lo, hi))
         g.close()
         self.info = None
+        self._streams = []
 
     def build_lets(self, theta=None):
         """LETs of every other domain for each domain; returns per domain
@@ -61,17 +62,34 @@ class Domains:
         self.theta = th
         return self.info
 
-    def forces(self, eps=None):
+    def forces(self, eps=None, acc=None, pot=None, streams=4):
         """(acc [N,3], pot [N]) in the caller order of the particles given to
-        the constructor: each domain's own walk plus its merged LET walk."""
+        the constructor: each domain's own walk plus its merged LET walk.
+        The domains write disjoint rows, so they run on up to `streams` HIP
+        streams at once (default priority), the tail of one domain's walk
+        overlapping the next; the caller's stream waits for all of them."""
         import torch
         e = self.eps if eps is None else float(eps)
         if self.info is None:
             self.build_lets()
-        acc = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
-        pot = torch.empty((self.n,), dtype=torch.float32, device="cuda")
-        for t, ids in zip(self.trees, self.ids):
-            t.force_let(self.theta, e, rows=ids, acc=acc, pot=pot)
+        if acc is None:
+            acc = torch.empty((self.n, 3), dtype=torch.float32, device="cuda")
+        if pot is None:
+            pot = torch.empty((self.n,), dtype=torch.float32, device="cuda")
+        cur = torch.cuda.current_stream()
+        k = max(1, min(int(streams), len(self.trees)))
+        if k == 1:
+            for t, ids in zip(self.trees, self.ids):
+                t.force_let(self.theta, e, rows=ids, acc=acc, pot=pot)
+            return acc, pot
+        if len(self._streams) < k:
+            self._streams += [torch.cuda.Stream() for _ in range(k - len(self._streams))]
+        for s in self._streams[:k]:
+            s.wait_stream(cur)
+        for i, (t, ids) in enumerate(zip(self.trees, self.ids)):
+            t.force_let(self.theta, e, rows=ids, acc=acc, pot=pot, stream=self._streams[i % k])
+        for s in self._streams[:k]:
+            cur.wait_stream(s)
         return acc, pot
 
     def close(self):
