@@ -27,7 +27,7 @@ Readings of the paper (it gives no formulas for these steps):
   * cost of a particle = 23 npp + 65 npc of its group's last walk;
   * cut j is the first particle where the running cost reaches j/p of the
     total, then clamped so no domain holds more than floor(cap n / p)
-    particles (cap = 1.3: "30% above the average");
+    particles (cap = 1.3: at most 30% above the average);
   * boundary cells: descend from the root through cells holding more than
     ncrit particles, stopping at cells of at most ncrit particles, leaves
     and the level L, the deepest at which the boundary tree has at most
