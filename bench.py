@@ -257,7 +257,7 @@ def adjoint(name="disk_halo_1m_adjoint", log=print):
 
 
 def domains(name="disk_halo_13m", ps=(2, 4, 8, 16), curve="ph", max_boundary=4096, reps=3,
-            log=print):
+            log=print, sampling=None):
     """The force evaluation split into p spatial domains on the one device
     (Sec. III.B): flop-weighted cuts, per-domain trees in the global box,
     boundary trees, merged local essential trees, own + LET walks; against
@@ -295,7 +295,12 @@ def domains(name="disk_halo_13m", ps=(2, 4, 8, 16), curve="ph", max_boundary=409
     for p in ps:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        d = bh.Domains(pos, mass, p, theta, eps, max_boundary=max_boundary, curve=curve)
+        smp = None
+        if sampling:
+            px = max(v for v in range(1, int(p ** 0.5) + 1) if p % v == 0)
+            smp = (px, p // px, sampling, sampling)
+        d = bh.Domains(pos, mass, p, theta, eps, max_boundary=max_boundary, curve=curve,
+                       sampling=smp)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         info = d.build_lets()
@@ -331,7 +336,9 @@ def domains(name="disk_halo_13m", ps=(2, 4, 8, 16), curve="ph", max_boundary=409
         allinfo = np.concatenate([i for i in info if len(i)]) if p > 1 else np.zeros((0, 3))
         let_cells = int(allinfo[:, 1].sum()) if len(allinfo) else 0
         let_parts = int(allinfo[:, 2].sum()) if len(allinfo) else 0
-        row = {"p": p, "cuts_sizes": np.diff(d.cuts).tolist(), "setup_s": t1 - t0,
+        row = {"p": p, "cut": "exact" if smp is None else
+               f"sampled {smp[0]}x{smp[1]}, {smp[2]} samples per process and level",
+               "cuts_sizes": np.diff(d.cuts).tolist(), "setup_s": t1 - t0,
                "let_build_s": t2 - t1, "force_ms": ms, "force_ms_one_stream": ms_serial,
                "domain_ms_max": float(dom_ms.max()),
                "domain_ms_min": float(dom_ms.min()),
@@ -343,8 +350,9 @@ def domains(name="disk_halo_13m", ps=(2, 4, 8, 16), curve="ph", max_boundary=409
                "pairs": p * (p - 1), "let_cells": let_cells, "let_particles": let_parts,
                "acc_rel_diff_vs_one_tree_median": float(np.median(err)),
                "acc_rel_diff_vs_one_tree_p99": float(np.percentile(err, 99))}
-        log(f"[bench] domains p={p}: force {ms:.1f} ms on 4 streams, {ms_serial:.1f} ms on "
-            f"one (one tree {call1:.1f}), "
+        log(f"[bench] domains p={p} ({row['cut']}): force {ms:.1f} ms on 4 streams, "
+            f"{ms_serial:.1f} ms on one (one tree {call1:.1f}), slowest/fastest domain "
+            f"{dom_ms.max():.2f}/{dom_ms.min():.2f} ms, "
             f"interactions x{inter / inter1:.3f}, LET build {t2 - t1:.2f} s, "
             f"boundary trees {row['boundary_sufficed']}/{row['pairs']}")
         rows.append(row)
@@ -372,6 +380,9 @@ def main(argv=None):
     ap.add_argument("--domains", type=str, default=None,
                     help="comma-separated domain counts: time the multi-domain force "
                          "(own + local-essential-tree walks) instead")
+    ap.add_argument("--sampling", type=int, default=0,
+                    help="with --domains: cut by the two-level sampling with this many "
+                         "samples per process and level (0: exact cut)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only run the differentiation workload and print its JSON object")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -414,7 +425,8 @@ def main(argv=None):
         return 0
     if args.domains:
         ps = tuple(int(v) for v in args.domains.split(","))
-        print(json.dumps(domains(args.workload, ps, args.curve, log=log)))
+        print(json.dumps(domains(args.workload, ps, args.curve, log=log,
+                                 sampling=args.sampling or None)))
         return 0
 
     w = ics.WORKLOADS[args.workload]

@@ -309,6 +309,26 @@ int bh_set_box(bh_ctx *ctx, const float *lo, float side);
  * C p < n), BH_ESTATE (no walk since the last build). */
 int bh_decompose(bh_ctx *ctx, int32_t p, float cap, int64_t *cuts, hipStream_t s);
 
+/* The same cut by the paper's two-level sampling (Sec. III.B.1), run on the
+ * host as one process would run it for p = px py processes.  Process q
+ * holds the particles whose caller index i has floor(i p / n) = q.  Level
+ * 1: every process draws m1 cost-weighted samples of its keys (sample j is
+ * the key of its first particle, in key order, at which the running cost S
+ * has 2 m1 S >= (2 j + 1) W_q, W_q its total cost; each sample weighs W_q);
+ * the samples, sorted by key (ties in process order), are cut into px
+ * pieces of equal weight (boundary t: the key of the first sample with the
+ * weight before it >= t/px of the total).  Level 2: every process draws m2
+ * samples the same way, each goes to the piece its key falls in, and each
+ * piece is cut into py pieces of equal weight.  The p - 1 boundary keys
+ * (host bounds [p - 1], may be NULL; a boundary with no sample past it is
+ * the next level-1 boundary, else 2^64 - 1) give cut j = the first sorted
+ * slot whose key is >= boundary j, clamped by the cap as in bh_decompose;
+ * equal keys never straddle a cut except by the clamp.  Synchronises s.
+ * Errors: as bh_decompose, and BH_EINVAL for px, py, m1 or m2 < 1 or
+ * px py > min(n, 65536). */
+int bh_decompose_sampled(bh_ctx *ctx, int32_t px, int32_t py, int32_t m1, int32_t m2, float cap,
+                         int64_t *cuts, uint64_t *bounds, hipStream_t s);
+
 /* Copy the particles in sorted slots [lo, hi) to device arrays in sorted
  * order: pos [hi - lo][3], vel [hi - lo][3], mass [hi - lo] and ids
  * [hi - lo] (the caller index of each); any output may be NULL.  This is

@@ -10,7 +10,8 @@ Steps (paper: Bedorf et al., SC14, arXiv:1412.0659):
                                 no piece above a cap on the particle count)
                                 with the operation counts of Sec. V.A (23 per
                                 particle-particle and 65 per particle-cell
-                                interaction)
+                                interaction): exact over all keys, and by the
+                                paper's two-level sampling
   domain trees                  Sec. III.B.1 (every domain keys its particles
                                 in the one global box, so each local tree is a
                                 branch of one global octree)
@@ -82,6 +83,95 @@ def decompose(cost, p: int, cap: float):
         cuts.append(min(max(t, lo), hi))
     cuts.append(n)
     return np.asarray(cuts, np.int64)
+
+
+def _samples(keys_local, cost_local, m):
+    """m cost-weighted samples of one process's keys (in key order): sample j
+    is the key of the particle whose cost interval holds the point
+    (j + 1/2) W / m of the process's total cost W."""
+    S = 0
+    out = []
+    W = int(sum(int(c) for c in cost_local))
+    j = 0
+    for k, c in zip(keys_local.tolist(), cost_local.tolist()):
+        S1 = S + int(c)
+        while j < m and 2 * m * S1 >= (2 * j + 1) * W:
+            out.append(k)
+            j += 1
+        S = S1
+    return out, W
+
+
+def _equal_weight_cuts(samples, pieces):
+    """Boundary keys cutting (key, weight) samples, sorted by key (ties in
+    input order), into `pieces` runs of equal total weight: boundary t is the
+    key of the first sample at which the weight before it reaches t / pieces
+    of the total."""
+    order = sorted(range(len(samples)), key=lambda i: samples[i][0])
+    T = sum(w for _, w in samples)
+    out = []
+    S = 0
+    t = 1
+    for i in order:
+        while t < pieces and S * pieces >= T * t:
+            out.append(samples[i][0])
+            t += 1
+        S += samples[i][1]
+    while t < pieces:
+        out.append(None)   # fewer samples than pieces: an empty piece at the end
+        t += 1
+    return out
+
+
+def decompose_sampled(skeys, cost, owner, px, py, m1, m2, cap):
+    """The two-level sampling cut (Sec. III.B.1) emulated in one process.
+    skeys: sorted keys, cost: cost of each sorted particle, owner: the process
+    (0 .. px py - 1) holding it.  Level 1: every process draws m1 cost-weighted
+    samples of its keys, each carrying its total cost W_q; one DD process cuts
+    them into px equal-weight pieces.  Level 2: every process draws m2
+    samples, each goes to the piece its key falls in, and each piece's DD
+    process cuts its samples into py pieces.  The p - 1 boundary keys give
+    the domains [B_d, B_{d+1}); the slots are clamped by the particle cap of
+    `decompose`.  Returns (cuts [p + 1], boundary keys [p - 1])."""
+    skeys = np.asarray(skeys, np.uint64)
+    cost = np.asarray(cost, np.int64)
+    owner = np.asarray(owner, np.int64)
+    n = skeys.shape[0]
+    p = px * py
+    C = int(np.floor(float(np.float32(cap)) * n / p))
+    if C * p < n:
+        raise ValueError("cap * n / p too small to hold n particles")
+    local = [np.nonzero(owner == q)[0] for q in range(p)]   # key order kept
+    s1 = []
+    for q in range(p):
+        ks, W = _samples(skeys[local[q]], cost[local[q]], m1)
+        s1 += [(k, W) for k in ks]
+    b1 = _equal_weight_cuts(s1, px)
+    top = [k for k in b1 if k is not None]
+    buckets = [[] for _ in range(px)]
+    for q in range(p):
+        ks, W = _samples(skeys[local[q]], cost[local[q]], m2)
+        for k in ks:
+            t = sum(1 for b in top if b <= k)   # the piece whose key range holds k
+            buckets[t].append((k, W))
+    # a missing boundary (fewer samples than pieces) closes its piece at the
+    # end of the enclosing range: the next top boundary, else past every key
+    big = int(np.iinfo(np.uint64).max)
+    tops = [big if b is None else int(b) for b in b1]
+    bk = []
+    for t in range(px):
+        if t > 0:
+            bk.append(tops[t - 1])
+        end = tops[t] if t < px - 1 else big
+        bk += [end if b is None else int(b) for b in _equal_weight_cuts(buckets[t], py)]
+    cuts = [0]
+    for j in range(1, p):
+        t = int(np.searchsorted(skeys, np.uint64(bk[j - 1]), side="left"))
+        lo = max(cuts[-1], n - (p - j) * C)
+        hi = min(cuts[-1] + C, n)
+        cuts.append(min(max(t, lo), hi))
+    cuts.append(n)
+    return np.asarray(cuts, np.int64), np.asarray(bk, np.uint64)
 
 
 # --- boundary tree (Sec. III.B.2) -------------------------------------------------

@@ -68,7 +68,7 @@ SYMBOLS = ["bh_create", "bh_destroy", "tree_build", "bh_set_state", "tree_force"
            "bh_strerror", "bh_last_error", "tree_force_vjp", "leapfrog_vjp_drift",
            "bh_state_bytes", "bh_save_state", "bh_load_state", "bh_cic_density",
            "bh_cic_density_vjp", "tree_direct", "bh_diagnostics", "bh_set_box",
-           "bh_decompose", "bh_domain_extract", "tree_force_add", "bh_boundary",
+           "bh_decompose", "bh_decompose_sampled", "bh_domain_extract", "tree_force_add", "bh_boundary",
            "bh_let_build", "tree_force_let"]
 
 _lib = None
@@ -115,6 +115,8 @@ def load():
         "bh_diagnostics": ([_vp, ctypes.POINTER(ctypes.c_double), _vp], c_int),
         "bh_set_box": ([_vp, _vp, f32], c_int),
         "bh_decompose": ([_vp, ctypes.c_int32, f32, _vp, _vp], c_int),
+        "bh_decompose_sampled": ([_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.c_int32, f32, _vp, _vp, _vp], c_int),
         "bh_domain_extract": ([_vp, i64, i64, _vp, _vp, _vp, _vp, _vp], c_int),
         "tree_force_add": ([_vp, _vp, f32, f32, _vp, _vp, _vp], c_int),
         "bh_boundary": ([_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -331,6 +333,17 @@ def bh_decompose(ctx, p, cap=1.3, stream=None) -> np.ndarray:
     return cuts
 
 
+def bh_decompose_sampled(ctx, px, py, m1, m2, cap=1.3, stream=None):
+    """Cuts [p + 1] and boundary keys [p - 1] of the two-level sampling."""
+    p = int(px) * int(py)
+    cuts = np.zeros(p + 1, np.int64)
+    bounds = np.zeros(max(p - 1, 1), np.uint64)
+    _check(ctx, load().bh_decompose_sampled(ctx, int(px), int(py), int(m1), int(m2), float(cap),
+                                            cuts.ctypes.data_as(_vp), bounds.ctypes.data_as(_vp),
+                                            _stream(stream)))
+    return cuts, bounds[:p - 1]
+
+
 def bh_domain_extract(ctx, lo, hi, pos=None, vel=None, mass=None, ids=None, stream=None):
     _check(ctx, load().bh_domain_extract(ctx, int(lo), int(hi), _ptr(pos), _ptr(vel),
                                          _ptr(mass), _u32ptr(ids), _stream(stream)))
@@ -485,6 +498,9 @@ class Tree:
 
     def decompose(self, p, cap=1.3) -> np.ndarray:
         return bh_decompose(self.ctx, p, cap)
+
+    def decompose_sampled(self, px, py, m1, m2, cap=1.3):
+        return bh_decompose_sampled(self.ctx, px, py, m1, m2, cap)
 
     def extract(self, lo, hi):
         """Particles of sorted slots [lo, hi): (pos, vel, mass, ids) tensors."""

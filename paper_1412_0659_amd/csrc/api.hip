@@ -137,6 +137,72 @@ int check_n(bh_ctx *c, int64_t n) {
     return BH_OK;
 }
 
+// Per sorted particle: 23 npp + 65 npc of its group's last walk (host).
+int particle_costs(bh_ctx *c, std::vector<int64_t> &cost) {
+    uint32_t ng = 0;
+    BH_HIP(c, hipMemcpy(&ng, c->groups.count_dev, sizeof(ng), hipMemcpyDeviceToHost));
+    std::vector<uint32_t> b((size_t)ng + 1), pp(ng), pc(ng);
+    BH_HIP(c, hipMemcpy(b.data(), c->groups.begin, 4 * ((size_t)ng + 1), hipMemcpyDeviceToHost));
+    BH_HIP(c, hipMemcpy(pp.data(), c->groups.npp, 4 * (size_t)ng, hipMemcpyDeviceToHost));
+    BH_HIP(c, hipMemcpy(pc.data(), c->groups.npc, 4 * (size_t)ng, hipMemcpyDeviceToHost));
+    cost.assign((size_t)c->n, 0);
+    for (uint32_t g = 0; g < ng; ++g)
+        for (uint32_t i = b[g]; i < b[g + 1]; ++i)
+            cost[i] = 23 * (int64_t)pp[g] + 65 * (int64_t)pc[g];
+    return BH_OK;
+}
+
+// clamp cuts[1..p-1] so that no domain holds more than C particles
+void clamp_cuts(int64_t *cuts, int32_t p, int64_t n, int64_t C) {
+    for (int32_t k = 1; k < p; ++k) {
+        const int64_t lo = std::max(cuts[k - 1], n - (int64_t)(p - k) * C);
+        const int64_t hi = std::min(cuts[k - 1] + C, n);
+        cuts[k] = std::min(std::max(cuts[k], lo), hi);
+    }
+    cuts[p] = n;
+}
+
+// m cost-weighted samples of one process's particles (key order): sample j
+// is the first particle whose inclusive running cost S has
+// 2 m S >= (2 j + 1) W, W the process total
+void draw_samples(const std::vector<uint64_t> &keys, const std::vector<int64_t> &cost,
+                  int32_t m, std::vector<uint64_t> &out, int64_t &W) {
+    W = 0;
+    for (int64_t v : cost) W += v;
+    out.clear();
+    __int128 S = 0;
+    int32_t j = 0;
+    for (size_t i = 0; i < keys.size() && j < m; ++i) {
+        S += cost[i];
+        while (j < m && (__int128)2 * m * S >= (__int128)(2 * j + 1) * W) {
+            out.push_back(keys[i]);
+            ++j;
+        }
+    }
+}
+
+// (key, weight) samples -> pieces - 1 boundary keys of equal weight; a
+// boundary past the last sample is reported missing (have = 0)
+void weight_cuts(std::vector<std::pair<uint64_t, int64_t>> smp, int32_t pieces,
+                 std::vector<uint64_t> &key, std::vector<char> &have) {
+    std::stable_sort(smp.begin(), smp.end(),
+                     [](const std::pair<uint64_t, int64_t> &a,
+                        const std::pair<uint64_t, int64_t> &b) { return a.first < b.first; });
+    __int128 T = 0, S = 0;
+    for (auto &e : smp) T += e.second;
+    key.assign((size_t)std::max(pieces - 1, 0), 0);
+    have.assign(key.size(), 0);
+    int32_t t = 1;
+    for (auto &e : smp) {
+        while (t < pieces && S * pieces >= T * t) {
+            key[(size_t)t - 1] = e.first;
+            have[(size_t)t - 1] = 1;
+            ++t;
+        }
+        S += e.second;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -630,12 +696,82 @@ int bh_decompose(bh_ctx *c, int32_t p, float cap, int64_t *cuts, hipStream_t s) 
         ++j;
     }
     delete[] hb;
-    for (int32_t k = 1; k < p; ++k) {
-        const int64_t lo = std::max(cuts[k - 1], n - (int64_t)(p - k) * C);
-        const int64_t hi = std::min(cuts[k - 1] + C, n);
-        cuts[k] = std::min(std::max(cuts[k], lo), hi);
+    clamp_cuts(cuts, p, n, C);
+    return check_status(c);
+}
+
+int bh_decompose_sampled(bh_ctx *c, int32_t px, int32_t py, int32_t m1, int32_t m2, float cap,
+                         int64_t *cuts, uint64_t *bounds, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!cuts) return fail(c, BH_EINVAL, "null pointer");
+    if (!c->built) return fail(c, BH_ESTATE, "bh_decompose_sampled before tree_build");
+    if (!c->counts_valid) return fail(c, BH_ESTATE, "bh_decompose_sampled needs a force walk");
+    const int64_t n = c->n;
+    if (px < 1 || py < 1 || (int64_t)px * py > n || (int64_t)px * py > 65536)
+        return fail(c, BH_EINVAL, "need 1 <= px py <= min(n, 65536)");
+    if (m1 < 1 || m2 < 1) return fail(c, BH_EINVAL, "sample counts must be >= 1");
+    const int32_t p = px * py;
+    if (!std::isfinite(cap) || !(cap >= 1.f)) return fail(c, BH_EINVAL, "cap must be >= 1");
+    const int64_t C = (int64_t)std::floor((double)cap * (double)n / (double)p);
+    if (C * (int64_t)p < n) return fail(c, BH_EINVAL, "cap * n / p cannot hold n particles");
+    BH_HIP(c, hipStreamSynchronize(s));
+    std::vector<int64_t> cost;
+    int rc = particle_costs(c, cost);
+    if (rc) return rc;
+    std::vector<uint64_t> skey((size_t)n);
+    std::vector<uint32_t> cid((size_t)n);
+    BH_HIP(c, hipMemcpy(skey.data(), c->sort.key[0], 8 * (size_t)n, hipMemcpyDeviceToHost));
+    BH_HIP(c, hipMemcpy(cid.data(), c->st[c->cur].cid, 4 * (size_t)n, hipMemcpyDeviceToHost));
+    // the emulated processes: caller index i is held by process floor(i p / n)
+    std::vector<std::vector<uint64_t>> lk((size_t)p);
+    std::vector<std::vector<int64_t>> lc((size_t)p);
+    for (int64_t i = 0; i < n; ++i) {
+        const size_t q = (size_t)((int64_t)cid[(size_t)i] * p / n);
+        lk[q].push_back(skey[(size_t)i]);
+        lc[q].push_back(cost[(size_t)i]);
     }
-    cuts[p] = n;
+    std::vector<uint64_t> smp;
+    int64_t W = 0;
+    // level 1: every process samples, one DD process cuts into px pieces
+    std::vector<std::pair<uint64_t, int64_t>> s1;
+    for (int32_t q = 0; q < p; ++q) {
+        draw_samples(lk[(size_t)q], lc[(size_t)q], m1, smp, W);
+        for (uint64_t k : smp) s1.push_back({k, W});
+    }
+    std::vector<uint64_t> top;
+    std::vector<char> top_have;
+    weight_cuts(s1, px, top, top_have);
+    std::vector<uint64_t> present;
+    for (size_t t = 0; t < top.size(); ++t)
+        if (top_have[t]) present.push_back(top[t]);
+    // level 2: every process samples again, each sample to the piece of its
+    // key; the DD process of each piece cuts it into py pieces
+    std::vector<std::vector<std::pair<uint64_t, int64_t>>> bucket((size_t)px);
+    for (int32_t q = 0; q < p; ++q) {
+        draw_samples(lk[(size_t)q], lc[(size_t)q], m2, smp, W);
+        for (uint64_t k : smp) {
+            const size_t t =
+                (size_t)(std::upper_bound(present.begin(), present.end(), k) - present.begin());
+            bucket[t].push_back({k, W});
+        }
+    }
+    const uint64_t kEnd = ~(uint64_t)0;  // past every key
+    std::vector<uint64_t> bk;
+    for (int32_t t = 0; t < px; ++t) {
+        if (t > 0) bk.push_back(top_have[(size_t)t - 1] ? top[(size_t)t - 1] : kEnd);
+        const uint64_t end = t < px - 1 && top_have[(size_t)t] ? top[(size_t)t] : kEnd;
+        std::vector<uint64_t> sub;
+        std::vector<char> sub_have;
+        weight_cuts(bucket[(size_t)t], py, sub, sub_have);
+        for (size_t k = 0; k < sub.size(); ++k) bk.push_back(sub_have[k] ? sub[k] : end);
+    }
+    cuts[0] = 0;
+    for (int32_t j = 1; j < p; ++j)
+        cuts[j] = (int64_t)(std::lower_bound(skey.begin(), skey.end(), bk[(size_t)j - 1]) -
+                            skey.begin());
+    clamp_cuts(cuts, p, n, C);
+    if (bounds)
+        for (int32_t j = 0; j + 1 < p; ++j) bounds[j] = bk[(size_t)j];
     return check_status(c);
 }
 

@@ -20,7 +20,10 @@ class Domains:
     then each domain gets its own tree, boundary tree and merged LET."""
 
     def __init__(self, pos, mass, p, theta, eps, vel=None, cap=1.3, max_boundary=1024,
-                 nleaf=16, ncrit=64, curve="morton", far_fp16=False):
+                 nleaf=16, ncrit=64, curve="morton", far_fp16=False, sampling=None):
+        """sampling = (px, py, m1, m2) cuts by the two-level sampling with
+        px * py = p processes and m1, m2 samples per process and level;
+        None cuts exactly over all keys."""
         n = int(mass.shape[0])
         self.n, self.p = n, int(p)
         self.theta, self.eps = float(theta), float(eps)
@@ -30,7 +33,14 @@ class Domains:
         else:
             g.set_state(pos, vel, mass)
         g.force(theta, eps)  # costs of the cut: this walk's interaction counts
-        self.cuts = g.decompose(self.p, cap)
+        self.bounds = None
+        if sampling is None:
+            self.cuts = g.decompose(self.p, cap)
+        else:
+            px, py, m1, m2 = sampling
+            if px * py != self.p:
+                raise ValueError("sampling needs px * py == p")
+            self.cuts, self.bounds = g.decompose_sampled(px, py, m1, m2, cap)
         box = g.export("box")
         self.lo, self.side = box[:3].copy(), float(box[3])
         self.trees, self.ids, self.slots = [], [], []

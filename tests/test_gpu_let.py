@@ -122,6 +122,28 @@ def test_decompose_and_extract_bit_exact(oracle, curve, p, cap):
         assert np.array_equal(dmass.cpu().numpy(), mass[doms[d]])
 
 
+@pytest.mark.parametrize("curve,px,py,m1,m2,cap", [("morton", 2, 4, 64, 32, 1.3),
+                                                   ("ph", 4, 4, 128, 128, 1.3),
+                                                   ("morton", 3, 1, 16, 8, 1.05),
+                                                   ("ph", 1, 5, 8, 200, 1.3)])
+def test_sampled_decompose_bit_exact(oracle, curve, px, py, m1, m2, cap):
+    pos, mass = _disk(30000)
+    theta, eps = 0.4, 0.01
+    g = oracle.build_tree(pos, mass, curve=curve)
+    _, _, npp, npc = oracle.walk(g, theta, eps)
+    cost = LT.particle_cost(g.n, g.gbeg, g.gcnt, npp, npc)
+    p = px * py
+    owner = g.perm * p // g.n
+    cuts, bounds = LT.decompose_sampled(g.skeys, cost, owner, px, py, m1, m2, cap)
+    t = gpu_tree(pos, mass, curve=curve)
+    gpu_force(t, theta, eps)
+    gcuts, gbounds = t.decompose_sampled(px, py, m1, m2, cap)
+    share = np.add.reduceat(cost, gcuts[:-1]) / (cost.sum() / p)
+    print(f"  {curve} {px}x{py} m={m1},{m2}: cuts {gcuts.tolist()}; cost share "
+          f"{share.min():.3f}-{share.max():.3f}", flush=True)
+    assert np.array_equal(gcuts, cuts) and np.array_equal(gbounds, bounds)
+
+
 def test_decompose_errors():
     from paper_1412_0659_amd import BhError
     pos, mass = _disk(3000)
@@ -132,6 +154,9 @@ def test_decompose_errors():
     for p, cap in ((0, 1.3), (4, 0.5), (7, 1.0), (5000, 1.3)):
         with pytest.raises(BhError):
             t.decompose(p, cap)
+    for args in ((0, 2, 4, 4), (2, 2, 0, 4), (2, 2, 4, 0), (3000, 2, 4, 4)):
+        with pytest.raises(BhError):
+            t.decompose_sampled(*args)
     from paper_1412_0659_amd import bh_domain_extract
     for lo, hi in ((10, 5), (-1, 5), (0, 3001)):
         with pytest.raises(BhError):
@@ -273,17 +298,24 @@ def test_far_clusters_use_boundary_trees(oracle):
         assert np.median(ea) < 2e-3 and np.percentile(ea, 99) < 2e-2
 
 
-@pytest.mark.parametrize("curve,p", [("morton", 4), ("ph", 10)])
-def test_domains_total_force(oracle, curve, p):
+@pytest.mark.parametrize("curve,p,sampling", [("morton", 4, None), ("ph", 10, None),
+                                              ("ph", 6, (2, 3, 48, 32))])
+def test_domains_total_force(oracle, curve, p, sampling):
     from paper_1412_0659_amd import Domains
     pos, mass = _disk(40000)
     theta, eps = 0.4, 0.01
-    d = Domains(to_dev(pos), to_dev(mass), p, theta, eps, max_boundary=256, curve=curve)
+    d = Domains(to_dev(pos), to_dev(mass), p, theta, eps, max_boundary=256, curve=curve,
+                sampling=sampling)
     info = d.build_lets()
     acc, pot = d.forces()
     import torch
     torch.cuda.synchronize()
     g, cuts, box, doms = _oracle_domains(oracle, pos, mass, p, curve, theta, eps)
+    if sampling is not None:
+        _, _, npp, npc = oracle.walk(g, theta, eps)
+        cost = LT.particle_cost(g.n, g.gbeg, g.gcnt, npp, npc)
+        cuts, _ = LT.decompose_sampled(g.skeys, cost, g.perm * p // g.n, *sampling, 1.3)
+        doms = [g.perm[cuts[k]:cuts[k + 1]] for k in range(p)]
     assert np.array_equal(d.cuts, cuts)
     oacc, opot, _ = LT.domain_forces(pos, mass, doms, box, theta, eps, curve)
     ea = rel_err(acc.cpu().numpy(), oacc)

@@ -73,6 +73,47 @@ def test_decompose_cap():
         LT.decompose(np.ones(10, np.int64), 3, 0.5)
 
 
+def test_sampled_cut_worked_examples():
+    """Keys 0..7, unit costs, two processes holding the even and the odd
+    keys, two samples each: process 0 samples keys 0 and 4 (running cost
+    1 >= 4/4 and 3 >= 12/4), process 1 keys 1 and 5; each sample weighs 4,
+    so half the weight (8) lies before key 4: one boundary, key 4."""
+    keys = np.arange(8, dtype=np.uint64)
+    cuts, b = LT.decompose_sampled(keys, np.ones(8, np.int64), np.arange(8) % 2, 2, 1, 2, 2,
+                                   1.3)
+    assert cuts.tolist() == [0, 4, 8] and b.tolist() == [4]
+    # keys 0..15 held by four processes (i mod 4), px = py = 2, two samples
+    # per process and level: level-1 samples 0,1,2,3,8,9,10,11 (weight 4)
+    # cut at key 8; the two pieces are cut at keys 2 and 10: slots 2, 8, 10.
+    # The cap (C = floor(1.3 * 16 / 4) = 5) moves them to 2, 7, 11.
+    keys = np.arange(16, dtype=np.uint64)
+    cuts, b = LT.decompose_sampled(keys, np.ones(16, np.int64), np.arange(16) % 4, 2, 2, 2, 2,
+                                   1.3)
+    assert b.tolist() == [2, 8, 10] and cuts.tolist() == [0, 2, 7, 11, 16]
+    cuts, _ = LT.decompose_sampled(keys, np.ones(16, np.int64), np.arange(16) % 4, 2, 2, 2, 2,
+                                   4.0)
+    assert cuts.tolist() == [0, 2, 8, 10, 16]
+
+
+@pytest.mark.parametrize("px,py", [(1, 4), (2, 4), (4, 4), (3, 1)])
+def test_sampled_cut_balances_cost(px, py):
+    rng = np.random.default_rng(11 + px * py)
+    n = 6000
+    keys = np.sort(rng.integers(0, 2 ** 50, size=n).astype(np.uint64))
+    keys[100:140] = keys[100]                  # a run of equal keys
+    cost = rng.integers(1, 200, size=n).astype(np.int64)
+    owner = rng.integers(0, px * py, size=n)
+    p = px * py
+    cuts, b = LT.decompose_sampled(keys, cost, owner, px, py, 256, 256, 4.0)
+    assert np.all(np.diff(b.astype(np.float64)) >= 0) and np.all(np.diff(cuts) >= 0)
+    share = np.add.reduceat(cost, cuts[:-1]) if p > 1 else np.array([cost.sum()])
+    assert np.all(np.abs(share / (cost.sum() / p) - 1) < 0.06)
+    for c in cuts[1:-1]:                         # equal keys stay together
+        assert c == 0 or c == n or keys[c - 1] != keys[c]
+    exact = LT.decompose(cost, p, 4.0)
+    assert np.all(np.abs(cuts - exact) <= 0.03 * n / p)
+
+
 # --- trees in a given box -----------------------------------------------------------
 
 def test_box_equal_to_own_bbox(oracle):
