@@ -353,7 +353,8 @@ def domains(name="disk_halo_13m", ps=(2, 4, 8, 16), curve="ph", max_boundary=409
         log(f"[bench] domains p={p} ({row['cut']}): force {ms:.1f} ms on 4 streams, "
             f"{ms_serial:.1f} ms on one (one tree {call1:.1f}), slowest/fastest domain "
             f"{dom_ms.max():.2f}/{dom_ms.min():.2f} ms, "
-            f"interactions x{inter / inter1:.3f}, LET build {t2 - t1:.2f} s, "
+            f"interactions x{inter / inter1:.3f}, LET build {t2 - t1:.3f} s "
+            f"({let_cells} cells, {let_parts} particles), "
             f"boundary trees {row['boundary_sufficed']}/{row['pairs']}")
         rows.append(row)
         d.close()
@@ -380,6 +381,8 @@ def main(argv=None):
     ap.add_argument("--domains", type=str, default=None,
                     help="comma-separated domain counts: time the multi-domain force "
                          "(own + local-essential-tree walks) instead")
+    ap.add_argument("--max-boundary", type=int, default=4096,
+                    help="with --domains: cell budget of each boundary tree")
     ap.add_argument("--sampling", type=int, default=0,
                     help="with --domains: cut by the two-level sampling with this many "
                          "samples per process and level (0: exact cut)")
@@ -425,7 +428,7 @@ def main(argv=None):
         return 0
     if args.domains:
         ps = tuple(int(v) for v in args.domains.split(","))
-        print(json.dumps(domains(args.workload, ps, args.curve, log=log,
+        print(json.dumps(domains(args.workload, ps, args.curve, args.max_boundary, log=log,
                                  sampling=args.sampling or None)))
         return 0
 
