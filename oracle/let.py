@@ -263,14 +263,17 @@ def prune(src: O.Tree, keep, expand):
 
 # --- remote walk (Sec. III.B.2) ---------------------------------------------------
 
-def walk_remote(tgt: O.Tree, src: O.Tree, theta: float, eps: float, cells=None):
-    """Forces on tgt's particles (caller order of tgt) from src's tree, and
-    per-group (npp, npc) of tgt's groups.  cells replaces src's topology
-    (count, nchild) by a pruned one; moments stay src's."""
+def walk_remote(tgt: O.Tree, src: O.Tree, theta: float, eps: float, cells=None, groups=None):
+    """Forces on tgt's particles (caller order of tgt; NaN outside the listed
+    groups) from src's tree, and per-group (npp, npc) of tgt's groups (-1
+    where not walked).  cells replaces src's topology (count, nchild) by a
+    pruned one; moments stay src's.  groups: tgt's groups to walk (all by
+    default)."""
     c = src.cells if cells is None else cells
     n = tgt.n
     ro2 = O.open_radius2(src.mom["lf"], src.mom["deltaf"], theta)
-    glist = np.arange(tgt.ngroups, dtype=np.int64)
+    glist = np.arange(tgt.ngroups, dtype=np.int64) if groups is None else \
+        np.ascontiguousarray(np.unique(groups), dtype=np.int64)
     acc_s = np.full(3 * n, np.nan)
     pot_s = np.full(n, np.nan)
     npp = np.full(tgt.ngroups, -1, np.int64)

@@ -335,6 +335,85 @@ def test_domains_total_force(oracle, curve, p, sampling):
     d.close()
 
 
+def test_domains_full_size(oracle):
+    """The 13M workload in eight domains, in the launch configuration of the
+    benchmark's domain mode: with cap 1.0 the cut is forced to equal counts
+    (n / 8 per domain) whatever the costs, so the oracle partitions the
+    particles by itself; the domain trees are compared bit for bit, one LET
+    cell set against the oracle's, and the own + LET forces of 150 seeded
+    groups per domain against the oracle's own + remote walks of those
+    groups."""
+    from paper_1412_0659_amd import Domains
+    name = "disk_halo_13m"
+    w = ics.WORKLOADS[name]
+    s = ics.make(name)
+    theta, eps, p = w["theta"], w["eps"], 8
+    print(f"case {name} n={s.n} p={p}", flush=True)
+    d = Domains(to_dev(s.pos), to_dev(s.mass), p, theta, eps, cap=1.0, max_boundary=4096)
+    info = d.build_lets()
+    acc, pot = d.forces()
+    acc = acc.cpu().numpy().astype(np.float64)
+    pot = pot.cpu().numpy().astype(np.float64)
+    step = s.n // p
+    assert d.cuts.tolist() == [k * step for k in range(p + 1)]
+    g = oracle.build_tree(s.pos, s.mass)
+    box = (g.lo, g.side)
+    doms = [g.perm[k * step:(k + 1) * step] for k in range(p)]
+    otrees = [oracle.build_tree(s.pos[ix], s.mass[ix], box=box) for ix in doms]
+    for k in (0, 5):
+        assert_tree_equal(d.trees[k], otrees[k])
+    # the LET domain 0 receives from domain 1
+    L0, inb0, term0 = LT.boundary(otrees[0], 4096)
+    L1, inb1, term1 = LT.boundary(otrees[1], 4096)
+    _, bc, bh = LT.boundary_boxes(otrees[0], term0, box)
+    vis, opn, ins = LT.let_mark(otrees[1], theta, bc, bh, term1)
+    origin = d.trees[0].export("let_origin").astype(np.int64)
+    keep = inb1 if not ins else vis
+    assert np.array_equal(np.sort(origin[origin[:, 0] == 0, 1]), np.nonzero(keep)[0])
+    assert info[0][0, 0] == (0 if ins else 1)
+    rng = np.random.default_rng(78)
+    errs_a, errs_p = [], []
+    for k in range(p):
+        ot = otrees[k]
+        sel = np.sort(rng.choice(ot.ngroups, size=150, replace=False))
+        oa, op, _, _ = oracle.walk(ot, theta, eps, groups=sel)
+        for e in range(p):
+            if e != k:
+                ra, rp, _, _, _ = LT.walk_remote(ot, otrees[e], theta, eps, groups=sel)
+                oa = oa + ra
+                op = op + rp
+        tl = np.concatenate([ot.perm[ot.gbeg[gg]:ot.gbeg[gg] + ot.gcnt[gg]] for gg in sel])
+        rows = doms[k][tl]
+        errs_a.append(rel_err(acc[rows], oa[tl]))
+        errs_p.append(rel_err(pot[rows], op[tl]))
+    ea, ep = np.concatenate(errs_a), np.concatenate(errs_p)
+    print(f"  {ea.shape[0]} targets: acc med {np.median(ea):.2e} p99 {np.percentile(ea, 99):.2e}"
+          f"  pot med {np.median(ep):.2e} p99 {np.percentile(ep, 99):.2e}", flush=True)
+    assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
+    assert np.median(ep) <= MED_TOL and np.percentile(ep, 99) <= P99_TOL
+    d.close()
+
+
+def test_tiny_domains(oracle):
+    """Many domains of a few particles each (36 sources per LET: two levels
+    of virtual cells; boundary trees of at most 16 cells)."""
+    from paper_1412_0659_amd import Domains
+    pos, mass = _disk(300)
+    theta, eps = 0.5, 0.01
+    for p in (16, 37):
+        d = Domains(to_dev(pos), to_dev(mass), p, theta, eps, max_boundary=16, cap=4.0)
+        d.build_lets()
+        acc, pot = d.forces()
+        acc = acc.cpu().numpy()
+        g, cuts, box, doms = _oracle_domains(oracle, pos, mass, p, "morton", theta, eps, 4.0)
+        assert np.array_equal(d.cuts, cuts)
+        oacc, opot, _ = LT.domain_forces(pos, mass, [ix for ix in doms if len(ix)], box, theta, eps)
+        ea = rel_err(acc, oacc)
+        print(f"  p={p}: {len(d.trees)} non-empty domains; acc med {np.median(ea):.2e}", flush=True)
+        assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
+        d.close()
+
+
 def test_let_errors():
     from paper_1412_0659_amd import BhError, Tree
     pos, mass = _disk(4000)
