@@ -257,7 +257,7 @@ def adjoint(name="disk_halo_1m_adjoint", log=print):
 
 
 def domains(name="disk_halo_13m", ps=(2, 4, 8, 16), curve="ph", max_boundary=4096, reps=3,
-            log=print, sampling=None):
+            log=print, sampling=None, snap=None):
     """The force evaluation split into p spatial domains on the one device
     (Sec. III.B): flop-weighted cuts, per-domain trees in the global box,
     boundary trees, merged local essential trees, own + LET walks; against
@@ -269,7 +269,8 @@ def domains(name="disk_halo_13m", ps=(2, 4, 8, 16), curve="ph", max_boundary=409
     from workloads import ics
     w = ics.WORKLOADS[name]
     theta, eps = w["theta"], w["eps"]
-    snap = ics.make(name)
+    if snap is None:
+        snap = ics.make(name)
     dev = torch.device("cuda:0")
     pos = torch.from_numpy(snap.pos).to(dev)
     mass = torch.from_numpy(snap.mass).to(dev)
@@ -374,6 +375,7 @@ def main(argv=None):
                     help="space-filling curve of the keys (the same cells either way)")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-domains", action="store_true")
     ap.add_argument("--precision-sweep", action="store_true",
                     help="only run the precision form's table (4M disk + halo, theta 0.3/0.4/0.6)")
     ap.add_argument("--param-sweep", action="store_true",
@@ -514,6 +516,21 @@ def main(argv=None):
         out["precision"].pop("_ref")
     if not args.no_adjoint:
         out["adjoint"] = adjoint(log=log)
+    if not args.no_domains:
+        r = domains(args.workload, (8,), args.curve, log=log, snap=snap)
+        row = r["rows"][0]
+        out["domains"] = {
+            "what": "the same force split into 8 spatial domains on this GPU: flop-weighted "
+                    "cuts, per-domain trees in the global box, boundary trees, merged local "
+                    "essential trees; own + LET walks of the domains on 4 streams",
+            "p": 8, "force_ms": row["force_ms"], "one_tree_force_ms": r["one_tree_force_ms"],
+            "force_ms_one_stream": row["force_ms_one_stream"],
+            "domain_ms_max": row["domain_ms_max"], "domain_ms_min": row["domain_ms_min"],
+            "interactions_over_one_tree": row["interactions_over_one_tree"],
+            "let_build_s": row["let_build_s"], "let_cells": row["let_cells"],
+            "let_particles": row["let_particles"],
+            "boundary_sufficed": row["boundary_sufficed"], "pairs": row["pairs"],
+            "acc_rel_diff_vs_one_tree_median": row["acc_rel_diff_vs_one_tree_median"]}
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(snap, theta, eps)

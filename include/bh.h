@@ -300,7 +300,7 @@ int bh_set_box(bh_ctx *ctx, const float *lo, float side);
  * (Sec. III.B.1: cuts that balance the tree-walk operations, no domain more
  * than a cap above the average particle count).  Needs a force walk of the
  * current tree.  Cost of a particle: 23 npp + 65 npc of its group's last
- * walk (the operation counts of Sec. V.A).  Cut j (host int64 cuts[p + 1],
+ * walk (the operation counts of Sec. VI.A).  Cut j (host int64 cuts[p + 1],
  * cuts[0] = 0, cuts[p] = n) is the first sorted slot i at which the running
  * cost of slots [0, i) reaches j/p of the total, clamped so that no domain
  * holds more than C = floor(cap n / p) particles: cuts[j] in

@@ -8,7 +8,7 @@ Steps (paper: Bedorf et al., SC14, arXiv:1412.0659):
   flop-weighted decomposition   Sec. III.B.1 (cut the space-filling curve into
                                 p pieces that balance the walk's operations,
                                 no piece above a cap on the particle count)
-                                with the operation counts of Sec. V.A (23 per
+                                with the operation counts of Sec. VI.A (23 per
                                 particle-particle and 65 per particle-cell
                                 interaction): exact over all keys, and by the
                                 paper's two-level sampling
@@ -51,7 +51,7 @@ PC_FLOPS = 65
 # --- decomposition (Sec. III.B.1) -------------------------------------------------
 
 def particle_cost(n, gbeg, gcnt, npp, npc):
-    """Per sorted particle: the walk operations of its group (Sec. V.A)."""
+    """Per sorted particle: the walk operations of its group (Sec. VI.A)."""
     cost = np.zeros(n, np.int64)
     w = PP_FLOPS * np.asarray(npp, np.int64) + PC_FLOPS * np.asarray(npc, np.int64)
     for b, c, wg in zip(np.asarray(gbeg, np.int64), np.asarray(gcnt, np.int64), w):
