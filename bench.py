@@ -244,16 +244,38 @@ def adjoint(name="disk_halo_1m_adjoint", log=print):
     loss.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    tree.close()
     fwd, bwd = t1 - t0, t2 - t1
     log(f"[bench] adjoint: forward {fwd:.2f} s, backward {bwd:.2f} s")
     finite = all(bool(torch.isfinite(a.grad).all()) for a in (x0, v0, m))
+    # the same with a snapshot after every step: no segment is recomputed
+    grads = [a.grad.clone() for a in (x0, v0, m)]
+    for a in (x0, v0, m):
+        a.grad = None
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    xK, _ = leapfrog(x0, v0, m, tree, w["dt"], w["steps"], w["theta"], w["eps"], 1)
+    loss1 = ((surface_density(xK, m, sel, tree, w["grid"]) - target) ** 2).sum()
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    loss1.backward()
+    torch.cuda.synchronize()
+    t5 = time.perf_counter()
+    same = all(torch.equal(a.grad, g) for a, g in zip((x0, v0, m), grads))
+    tree.close()
+    fwd1, bwd1 = t4 - t3, t5 - t4
+    snap_mb = w["steps"] * s.n * tree.snapshot_bytes(1) / 1e6
+    log(f"[bench] adjoint, snapshot every step: forward {fwd1:.2f} s, backward {bwd1:.2f} s, "
+        f"gradients identical: {same}")
     return {"workload": name, "n": s.n, "steps": w["steps"], "checkpoint_every": w["every"],
             "theta": w["theta"], "eps": w["eps"], "dt": w["dt"], "grid": list(w["grid"]),
             "loss": float(loss.detach()), "forward_s": fwd, "backward_s": bwd,
             "backward_over_forward": bwd / fwd,
             "ms_per_step_forward": 1e3 * fwd / w["steps"],
-            "ms_per_step_backward": 1e3 * bwd / w["steps"], "grad_finite": finite}
+            "ms_per_step_backward": 1e3 * bwd / w["steps"], "grad_finite": finite,
+            "every_step_snapshots": {"forward_s": fwd1, "backward_s": bwd1,
+                                     "backward_over_forward": bwd1 / fwd1,
+                                     "snapshot_mb": snap_mb,
+                                     "gradients_identical_to_every_8": same}}
 
 
 def domains(name="disk_halo_13m", ps=(2, 4, 8, 16), curve="ph", max_boundary=4096, reps=3,

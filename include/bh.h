@@ -372,7 +372,9 @@ int bh_boundary(bh_ctx *ctx, int32_t max_cells, int32_t *level, int64_t *nterm,
  * the full source tree.  Host info [nsrc][3] (may be NULL) receives per
  * source: 1 if the boundary tree sufficed, LET cells, LET particles.  Valid
  * until ctx's next build; the LET copies the sources, which may change
- * afterwards.  Synchronises s.  Errors: BH_EINVAL (nsrc, theta, a source
+ * afterwards.  Writes the sources' opening radii for theta (as their own
+ * tree_force would), so no source may be in use on another stream meanwhile.
+ * Synchronises s.  Errors: BH_EINVAL (nsrc, theta, a source
  * that is ctx or repeated, different boxes or devices), BH_ESTATE (missing
  * boundary tree), BH_ECAPACITY (more than 2^29 cells), BH_ENOMEM. */
 int bh_let_build(bh_ctx *ctx, bh_ctx *const *srcs, int32_t nsrc, float theta, int64_t *info,

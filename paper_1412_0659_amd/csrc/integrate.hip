@@ -286,9 +286,18 @@ __global__ __launch_bounds__(256) void k_totals(const uint32_t *__restrict__ gbe
         spp += __shfl_xor(spp, d, 64);
         spc += __shfl_xor(spc, d, 64);
     }
+    // one pair of atomics per block: the counters are shared by every block
+    __shared__ unsigned long long part[4][2];
+    const uint32_t w = threadIdx.x >> 6;
     if (lane_id() == 0) {
-        atomicAdd(&tot[0], spp);
-        atomicAdd(&tot[1], spc);
+        part[w][0] = spp;
+        part[w][1] = spc;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        unsigned long long v = part[0][threadIdx.x] + part[1][threadIdx.x] +
+                               part[2][threadIdx.x] + part[3][threadIdx.x];
+        atomicAdd(&tot[threadIdx.x], v);
     }
 }
 
@@ -318,8 +327,9 @@ __global__ void k_zero_totals(unsigned long long *tot) {
 
 void launch_totals(bh_ctx *c, uint32_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_totals, dim3(1), dim3(64), 0, st, c->totals);
-    uint32_t nb = cdiv(n, 256);
-    if (nb > 1024) nb = 1024;
+    uint32_t nb = cdiv(n, 256 * 64);
+    if (nb > 256) nb = 256;
+    if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_totals, dim3(nb), dim3(256), 0, st, (const uint32_t *)c->groups.begin,
                        (const uint32_t *)c->groups.count_dev, (const uint32_t *)c->groups.npp,
                        (const uint32_t *)c->groups.npc, c->totals);
