@@ -15,6 +15,7 @@
 namespace bh {
 
 constexpr int kBuildThreads = 256;
+constexpr uint32_t kFewCells = 16384;  // levels with fewer cells are latency bound
 
 __device__ __forceinline__ uint32_t key_lower_bound(const uint64_t *__restrict__ k, uint32_t lo,
                                                     uint32_t hi, uint64_t v) {
@@ -27,15 +28,38 @@ __device__ __forceinline__ uint32_t key_lower_bound(const uint64_t *__restrict__
 }
 
 // digit boundaries of the children of cell c (level l): bnd[0] = begin,
-// bnd[8] = end; child d holds [bnd[d], bnd[d+1])
+// bnd[8] = end; child d holds [bnd[d], bnd[d+1]).  On a level of few cells
+// (latency bound: the top of the tree) a large range runs the seven
+// searches in lock step over the whole range, so their loads overlap
+// instead of waiting on each other; otherwise the searches are chained,
+// each starting at the previous bound (fewer loads).
 __device__ __forceinline__ void child_bounds(const uint64_t *__restrict__ key, uint64_t P,
-                                             uint32_t b, uint32_t e, int l, uint32_t bnd[9]) {
+                                             uint32_t b, uint32_t e, int l, bool few,
+                                             uint32_t bnd[9]) {
     uint32_t shift = 3u * (kKeyBits - 1 - l);
     bnd[0] = b;
+    bnd[8] = e;
+    if (few && e - b >= 256u) {
+        uint32_t base[8];
+#pragma unroll
+        for (uint32_t d = 1; d < 8; ++d) base[d] = b;
+        uint32_t len = e - b;
+        while (len > 1u) {
+            const uint32_t half = len >> 1;
+#pragma unroll
+            for (uint32_t d = 1; d < 8; ++d)
+                base[d] = key[base[d] + half] < (((P << 3) | d) << shift) ? base[d] + half
+                                                                          : base[d];
+            len -= half;
+        }
+#pragma unroll
+        for (uint32_t d = 1; d < 8; ++d)
+            bnd[d] = base[d] + (key[base[d]] < (((P << 3) | d) << shift) ? 1u : 0u);
+        return;
+    }
 #pragma unroll
     for (uint32_t d = 1; d < 8; ++d)
         bnd[d] = key_lower_bound(key, bnd[d - 1], e, ((P << 3) | d) << shift);
-    bnd[8] = e;
 }
 
 __global__ void k_build_init(Cells c, uint32_t n) {
@@ -65,6 +89,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_count(Cells c,
     __shared__ uint32_t lds[4];
     uint32_t cs, ce;
     level_chunk(c, l, cs, ce);
+    const bool few = c.ls[l + 1] - c.ls[l] < kFewCells;
     uint32_t sum = 0;
     for (uint32_t i = cs + threadIdx.x; i < ce; i += kBuildThreads) {
         uint32_t nch = 0;
@@ -72,7 +97,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_count(Cells c,
         if (cnt > nleaf) {
             uint32_t bnd[9];
             uint32_t b = c.begin[i];
-            child_bounds(key, c.prefix[i], b, b + cnt, l, bnd);
+            child_bounds(key, c.prefix[i], b, b + cnt, l, few, bnd);
 #pragma unroll
             for (int d = 0; d < 8; ++d) nch += bnd[d + 1] > bnd[d];
         }
@@ -127,6 +152,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_write(Cells c,
     __shared__ uint32_t lds[4];
     uint32_t cs, ce;
     level_chunk(c, l, cs, ce);
+    const bool few = c.ls[l + 1] - c.ls[l] < kFewCells;
     uint32_t carry = c.ls[l + 1] + c.part[blockIdx.x];
     uint32_t lane = lane_id(), w = threadIdx.x >> 6;
     for (uint32_t base = cs; base < ce; base += kBuildThreads) {
@@ -147,7 +173,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_write(Cells c,
             uint32_t b = c.begin[i];
             uint64_t P = c.prefix[i];
             uint32_t bnd[9];
-            child_bounds(key, P, b, b + c.count[i], l, bnd);
+            child_bounds(key, P, b, b + c.count[i], l, few, bnd);
             for (uint32_t d = 0; d < 8; ++d) {
                 if (bnd[d + 1] > bnd[d]) {
                     if (ch < cap) {

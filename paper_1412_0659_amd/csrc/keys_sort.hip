@@ -214,24 +214,48 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
         rk[r] = run + before;
     }
     __syncthreads();
+    // the tile reordered by digit in LDS: digit d starts at lo[d] (an
+    // exclusive scan of the tile's digit counts), wave w's keys of digit d
+    // after those of the waves before it; then written out in LDS order,
+    // so that consecutive threads store consecutive keys of one digit run
+    // (whole cache lines) instead of one key per run
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sidx[kSortTile];
+    __shared__ uint32_t wsum[4];
+    __shared__ int32_t delta[256];
     {
-        uint32_t d = threadIdx.x;
-        uint32_t g = offsets[(uint64_t)d * ntiles + blockIdx.x];
-        uint32_t c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d];
+        const uint32_t d = threadIdx.x;
+        const uint32_t c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d], c3 = cnt[3][d];
+        const uint32_t tot = c0 + c1 + c2 + c3;
+        const uint32_t inc = wave_incl_scan(tot, lane);
+        if (lane == 63) wsum[w] = inc;
         __syncthreads();
-        cnt[0][d] = g;
-        cnt[1][d] = g + c0;
-        cnt[2][d] = g + c0 + c1;
-        cnt[3][d] = g + c0 + c1 + c2;
+        uint32_t lo = inc - tot;
+        for (uint32_t k = 0; k < w; ++k) lo += wsum[k];
+        const uint32_t g = offsets[(uint64_t)d * ntiles + blockIdx.x];
+        delta[d] = (int32_t)(g - lo);
+        cnt[0][d] = lo;
+        cnt[1][d] = lo + c0;
+        cnt[2][d] = lo + c0 + c1;
+        cnt[3][d] = lo + c0 + c1 + c2;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortRounds; ++r) {
         if (dd[r] < 256u) {
-            uint32_t pos = cnt[w][dd[r]] + rk[r];
-            key_out[pos] = kk[r];
-            idx_out[pos] = vv[r];
+            const uint32_t lp = cnt[w][dd[r]] + rk[r];
+            skey[lp] = kk[r];
+            sidx[lp] = vv[r];
         }
+    }
+    __syncthreads();
+    const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
+    const uint32_t valid = n - t0 < (uint64_t)kSortTile ? (uint32_t)(n - t0) : (uint32_t)kSortTile;
+    for (uint32_t t = threadIdx.x; t < valid; t += kSortThreads) {
+        const uint64_t k = skey[t];
+        const uint32_t pos = (uint32_t)(delta[(uint32_t)(k >> shift) & 255u] + (int32_t)t);
+        key_out[pos] = k;
+        idx_out[pos] = sidx[t];
     }
 }
 
