@@ -62,7 +62,7 @@ void free_all(bh_ctx *c) {
     f(b.flag); f(b.scan); f(b.ids); f(b.box); f(b.cmin); f(b.cmax); f(b.lvl); f(b.part);
     Let &t = c->let;
     f(t.wA); f(t.P0); f(t.P1); f(t.P2); f(t.xyzm); f(t.wN); f(t.origin);
-    f(t.cmark); f(t.cscan); f(t.pmark); f(t.pscan); f(t.spart); f(t.word);
+    f(t.cmark); f(t.omark); f(t.cscan); f(t.pmark); f(t.pscan); f(t.spart); f(t.word);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
 }
@@ -920,9 +920,10 @@ int bh_let_build(bh_ctx *c, bh_ctx *const *srcs, int32_t nsrc, float theta, int6
     (void)c6;
     t.cell_cap = need_c;
     t.part_cap = std::max<int64_t>(need_p, 1);
-    int64_t s1 = t.scr_cells, s2 = s1, s3 = t.scr_parts, s4 = s3, s5 = t.part_len, s6 = 1;
+    int64_t s1 = t.scr_cells, s2 = s1, s0 = s1, s3 = t.scr_parts, s4 = s3, s5 = t.part_len, s6 = 1;
     const int64_t plen = scan_part_len(std::max(max_c, max_p) + 1);
-    if (!grow(&t.cmark, s1, max_c + 1, err) || !grow(&t.cscan, s2, max_c + 1, err) ||
+    if (!grow(&t.cmark, s1, max_c + 1, err) || !grow(&t.omark, s0, max_c + 1, err) ||
+        !grow(&t.cscan, s2, max_c + 1, err) ||
         !grow(&t.pmark, s3, max_p + 1, err) || !grow(&t.pscan, s4, max_p + 1, err) ||
         !grow(&t.spart, s5, plen, err) || (!t.word && !grow(&t.word, s6, 1, err))) {
         t.scr_cells = t.scr_parts = t.part_len = 0;

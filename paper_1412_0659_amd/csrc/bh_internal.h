@@ -94,6 +94,7 @@ struct Let {
     // per-source scratch, sized to the largest source
     int64_t scr_cells = 0, scr_parts = 0, part_len = 0;
     uint32_t *cmark = nullptr;  // [cells + 1] bit 0 accepted, 1 opened, 2 reached
+    uint32_t *omark = nullptr;  // [cells + 1] leaves some box opened
     uint32_t *cscan = nullptr;  // [cells + 1] kept cells, scanned
     uint32_t *pmark = nullptr;  // [parts + 1] particles of opened leaves
     uint32_t *pscan = nullptr;  // [parts + 1]

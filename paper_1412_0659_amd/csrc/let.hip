@@ -13,9 +13,9 @@
 //
 // LET of a source tree for a target domain: every target box walks the
 // source tree with the force walk's own traversal and opening test.  Cells
-// the boxes accept and particles of the leaves they open are marked; a pass
-// up the levels then gives, per cell, whether some box opened it and
-// whether some box reached it.  Any target group lies inside one terminal
+// the boxes accept and the leaves they open are marked; a pass up the
+// levels then gives, per cell, whether some box opened it and whether some
+// box reached it, and marks the particles of opened leaves.  Any target group lies inside one terminal
 // box, and the margin keeps its FP32 box distance to any cell at least the
 // box's, so a group opens only cells that its box opens: the reached cells
 // (opened cells with all their children, opened leaves with their particles)
@@ -174,9 +174,9 @@ void launch_bnd_boxes(bh_ctx *c, uint32_t nc, uint32_t nterm, hipStream_t st) {
 // ---- local essential tree ---------------------------------------------------
 
 // One wave per target box (grid-stride): the force walk's traversal of the
-// source tree; accepted cells and particles of opened leaves are marked.
+// source tree; accepted cells (cmark) and opened leaves (omark) are marked.
 __global__ __launch_bounds__(64) void k_let_mark(TreeView tv, const float4 *__restrict__ tbox,
-                                                 uint32_t nbox, uint32_t *cmark, uint32_t *pmark,
+                                                 uint32_t nbox, uint32_t *cmark, uint32_t *omark,
                                                  uint32_t *spill_base) {
     __shared__ TravLds L;
     const uint32_t lane = threadIdx.x;
@@ -187,21 +187,23 @@ __global__ __launch_bounds__(64) void k_let_mark(TreeView tv, const float4 *__re
         b.cx = bc.x; b.cy = bc.y; b.cz = bc.z;
         b.hx = bh.x; b.hy = bh.y; b.hz = bh.z;
         uint32_t npc = 0, npp = 0;
-        traverse(
+        traverse<true>(
             tv, b, lane, L, spill, npc, npp,
             [&](uint32_t n) {
                 for (uint32_t i = lane; i < n; i += 64u) cmark[L.pcidx[i]] = 1u;
             },
             [&](uint32_t n) {
-                for (uint32_t i = lane; i < n; i += 64u) pmark[L.ppidx[i]] = 1u;
+                for (uint32_t i = lane; i < n; i += 64u) omark[L.ppidx[i]] = 1u;
             });
     }
 }
 
-// Level l, after level l + 1: opened = a leaf whose particles are marked or
-// an internal cell with a reached child; reached = accepted or opened.
+// Level l, after level l + 1: opened = a marked leaf or an internal cell
+// with a reached child; reached = accepted or opened.  The particles of an
+// opened leaf are marked in pmark.
 __global__ __launch_bounds__(256) void k_let_up(Cells c, int l, uint32_t *cmark,
-                                                const uint32_t *__restrict__ pmark,
+                                                const uint32_t *__restrict__ omark,
+                                                uint32_t *__restrict__ pmark,
                                                 const uint32_t *__restrict__ bflag,
                                                 uint32_t *word) {
     const uint32_t first = c.ls[l], last = c.ls[l + 1];
@@ -210,7 +212,11 @@ __global__ __launch_bounds__(256) void k_let_up(Cells c, int l, uint32_t *cmark,
         const uint32_t nch = c.nchild[i];
         bool opn = false;
         if (nch == 0u) {
-            opn = pmark[c.begin[i]] != 0u;
+            opn = omark[i] != 0u;
+            if (opn) {
+                const uint32_t b = c.begin[i], e = b + c.count[i];
+                for (uint32_t j = b; j < e; ++j) pmark[j] = 1u;
+            }
         } else {
             const uint32_t k0 = c.child0[i];
             for (uint32_t k = k0; k < k0 + nch; ++k) opn = opn || (cmark[k] & 4u) != 0u;
@@ -293,6 +299,7 @@ void launch_let_mark(bh_ctx *tgt, const bh_ctx *src, uint32_t nc, hipStream_t st
     Let &t = tgt->let;
     const uint32_t n = (uint32_t)src->n;
     launch_fill_u32(t.cmark, 0u, (uint64_t)nc + 1, st);
+    launch_fill_u32(t.omark, 0u, (uint64_t)nc + 1, st);
     launch_fill_u32(t.pmark, 0u, (uint64_t)n + 1, st);
     launch_fill_u32(t.word, 0u, 1, st);
     const uint32_t nbox = tgt->bnd.nterm;
@@ -304,11 +311,12 @@ void launch_let_mark(bh_ctx *tgt, const bh_ctx *src, uint32_t nc, hipStream_t st
         tv.status = tgt->status;
         const uint32_t grid = nbox < (uint32_t)tgt->walk_grid ? nbox : (uint32_t)tgt->walk_grid;
         hipLaunchKernelGGL(k_let_mark, dim3(grid), dim3(64), 0, st, tv,
-                           (const float4 *)tgt->bnd.box, nbox, t.cmark, t.pmark, tgt->spill);
+                           (const float4 *)tgt->bnd.box, nbox, t.cmark, t.omark, tgt->spill);
     }
     for (int l = kLevels - 1; l >= 0; --l)
         hipLaunchKernelGGL(k_let_up, dim3(kGrid), dim3(256), 0, st, src->cells, l, t.cmark,
-                           (const uint32_t *)t.pmark, (const uint32_t *)src->bnd.flag, t.word);
+                           (const uint32_t *)t.omark, t.pmark, (const uint32_t *)src->bnd.flag,
+                           t.word);
 }
 
 void launch_let_keep(bh_ctx *tgt, const bh_ctx *src, uint32_t nc, bool boundary_only,

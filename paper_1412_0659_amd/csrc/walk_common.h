@@ -85,8 +85,10 @@ __device__ __forceinline__ void plan_phases(uint32_t gn, uint32_t &T1, uint32_t 
 // Walk the tree for one group.  flush_pc(n) / flush_pp(n) evaluate the first
 // n entries of L.pcidx / L.ppidx (called with n > 0, all lanes, after a
 // barrier); both lists are empty when traverse returns.  Counts: accepted
-// cells and particles of opened leaves.
-template <class FlushPc, class FlushPp>
+// cells and particles of opened leaves.  kLeafCells: L.ppidx lists the
+// opened leaf cells themselves instead of their particles (and the second
+// count is of those leaves).
+template <bool kLeafCells = false, class FlushPc, class FlushPp>
 __device__ __forceinline__ void traverse(const TreeView &tv, const GroupBox &b, uint32_t lane,
                                          TravLds &L, uint32_t *spill, uint32_t &cnt_pc,
                                          uint32_t &cnt_pp, FlushPc &&flush_pc,
@@ -177,8 +179,21 @@ __device__ __forceinline__ void traverse(const TreeView &tv, const GroupBox &b, 
         }
         sp = sp_new + npush;
 
+        // ---- opened leaves -> their cells (kLeafCells)
+        if constexpr (kLeafCells) {
+            if (pp_n + 64u > (uint32_t)kPpCap) {
+                __syncthreads();
+                flush_pp(pp_n);
+                pp_n = 0;
+            }
+            const uint64_t lm = ballot(openleaf);
+            if (openleaf) L.ppidx[pp_n + count_below(lm)] = cell;
+            const uint32_t nl = (uint32_t)__popcll(lm);
+            pp_n += nl;
+            cnt_pp += nl;
+        }
         // ---- particles of opened leaves -> particle-particle index list
-        const uint32_t lc = openleaf ? (N.y & ~kLeafBit) : 0u;
+        const uint32_t lc = (!kLeafCells && openleaf) ? (N.y & ~kLeafBit) : 0u;
         const uint32_t lincl = wave_incl_scan(lc, lane);
         const uint32_t P = read_lane(lincl, 63u);
         if (P > 0u) {
