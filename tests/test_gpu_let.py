@@ -414,6 +414,56 @@ def test_tiny_domains(oracle):
         d.close()
 
 
+@pytest.mark.parametrize("seed", [201, 202, 203, 204, 205, 206])
+def test_let_seeded_configurations(oracle, seed):
+    """Seeded mixes of size, domain count, boundary budget, opening angle,
+    softening, tree parameters and curve: every LET cell set and sufficiency
+    decision bit-exact, the own + LET forces to the walk tolerance."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(3000, 25000))
+    p = int(rng.integers(2, 7))
+    max_cells = int(rng.choice([1, 8, 64, 300, 2048]))
+    theta = float(rng.choice([0.3, 0.5, 0.7, 1.0]))
+    eps = float(rng.choice([0.0, 0.003, 0.02]))
+    nleaf, ncrit = [(16, 64), (8, 32), (1, 4), (32, 64)][int(rng.integers(0, 4))]
+    curve = ["morton", "ph"][int(rng.integers(0, 2))]
+    pos, mass = (_clusters(n // 4, seed) if seed % 3 == 0 else _disk(n, seed))
+    print(f"  seed {seed}: n={pos.shape[0]} p={p} max_cells={max_cells} theta={theta} "
+          f"eps={eps} nleaf={nleaf} ncrit={ncrit} {curve}", flush=True)
+    from paper_1412_0659_amd import Tree
+    g = oracle.build_tree(pos, mass, nleaf, ncrit, curve=curve)
+    box = (g.lo, g.side)
+    cuts = np.linspace(0, g.n, p + 1).astype(np.int64)
+    doms = [g.perm[cuts[k]:cuts[k + 1]] for k in range(p)]
+    otrees = [oracle.build_tree(pos[ix], mass[ix], nleaf, ncrit, curve=curve, box=box)
+              for ix in doms]
+    obnd = [LT.boundary(ot, max_cells, ncrit) for ot in otrees]
+    trees = []
+    for ix in doms:
+        t = Tree(len(ix), nleaf, ncrit, curve=curve)
+        t.set_box(*box)
+        t.build(to_dev(pos[ix]), to_dev(mass[ix]))
+        t.boundary(max_cells)
+        trees.append(t)
+    for a in range(p):
+        others = [b for b in range(p) if b != a]
+        info = trees[a].let_build([trees[b] for b in others], theta)
+        origin = trees[a].export("let_origin").astype(np.int64)
+        _, bc, bh = LT.boundary_boxes(otrees[a], obnd[a][2], box)
+        oa, op, _, _ = oracle.walk(otrees[a], theta, eps)
+        for k, b in enumerate(others):
+            vis, opn, ins = LT.let_mark(otrees[b], theta, bc, bh, obnd[b][2])
+            keep = obnd[b][1] if not ins else vis
+            assert np.array_equal(np.sort(origin[origin[:, 0] == k, 1]), np.nonzero(keep)[0])
+            assert info[k, 0] == (0 if ins else 1)
+            ra, rp, _, _, _ = LT.walk_remote(otrees[a], otrees[b], theta, eps)
+            oa, op = oa + ra, op + rp
+        acc, pot = trees[a].force_let(theta, eps)
+        trees[a].sync()
+        ea = rel_err(acc.cpu().numpy(), oa)
+        assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL, (a, np.median(ea))
+
+
 def test_let_errors():
     from paper_1412_0659_amd import BhError, Tree
     pos, mass = _disk(4000)
