@@ -273,12 +273,15 @@ def adjoint(name="disk_halo_1m_adjoint", log=print):
     loss1.backward()
     torch.cuda.synchronize()
     t5 = time.perf_counter()
-    same = all(torch.equal(a.grad, g) for a, g in zip((x0, v0, m), grads))
+    # the FP64 atomic sums of the force VJP run in a varying order, so the two
+    # sweeps agree to rounding, not bit for bit
+    diff = max(float((a.grad - g).abs().max() / g.abs().max())
+               for a, g in zip((x0, v0, m), grads))
     tree.close()
     fwd1, bwd1 = t4 - t3, t5 - t4
     snap_mb = w["steps"] * s.n * tree.snapshot_bytes(1) / 1e6
     log(f"[bench] adjoint, snapshot every step: forward {fwd1:.2f} s, backward {bwd1:.2f} s, "
-        f"gradients identical: {same}")
+        f"gradients within {diff:.1e} of the every-8 sweep's")
     return {"workload": name, "n": s.n, "steps": w["steps"], "checkpoint_every": w["every"],
             "theta": w["theta"], "eps": w["eps"], "dt": w["dt"], "grid": list(w["grid"]),
             "loss": float(loss.detach()), "forward_s": fwd, "backward_s": bwd,
@@ -288,7 +291,7 @@ def adjoint(name="disk_halo_1m_adjoint", log=print):
             "every_step_snapshots": {"forward_s": fwd1, "backward_s": bwd1,
                                      "backward_over_forward": bwd1 / fwd1,
                                      "snapshot_mb": snap_mb,
-                                     "gradients_identical_to_every_8": same}}
+                                     "grad_max_rel_diff_vs_every_8": diff}}
 
 
 def domains(name="disk_halo_13m", ps=(2, 4, 8, 16), curve="ph", max_boundary=4096, reps=3,
