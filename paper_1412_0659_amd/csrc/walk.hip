@@ -34,28 +34,28 @@ __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v);
 
 // One particle-cell term, Eq. (1)-(2) with r^2 -> r^2 + eps^2.
 // A = (com x, y, z, M); B = (-3 Qxx, -3 Qyy, -3 Qzz, -3 Qxy);
-// C = (-3 Qxz, -3 Qyz, tr Q / 2, -3 tr Q / 2).  With q = -3 Q d:
-//   phi += -M/r + (tr/2)/r^3 + (1/2) d.q / r^5
+// C = (-3 Qxz, -3 Qyz, tr Q / 2, -3 tr Q / 2).  With q = -3 Q d and
+// w = d.q / r^2, in nested form (35 VALU operations and one rsq):
+//   phi += -M/r + (tr/2)/r^3 + (1/2) d.q / r^5 = [-M + (tr/2 + w/2) / r^2] / r
 //   a   += d [M/r^3 - (3/2) tr/r^5 - (5/2) d.q / r^7] + q / r^5
+//        = d [M + (-3 tr/2 - 5 w/2) / r^2] / r^3 + q / r^5
 __device__ __forceinline__ void pc_term(const float4 &T, const float4 &A, const float4 &B,
                                         const float4 &C, float eps2, float4 &acc) {
     float dx = A.x - T.x, dy = A.y - T.y, dz = A.z - T.z;
     float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
     float ri = rsq(r2);
     float ri2 = ri * ri;
-    float mr = A.w * ri;
     float ri3 = ri * ri2;
     float ri5 = ri3 * ri2;
     float qx = fmaf(B.x, dx, fmaf(B.w, dy, C.x * dz));
     float qy = fmaf(B.w, dx, fmaf(B.y, dy, C.y * dz));
     float qz = fmaf(C.x, dx, fmaf(C.y, dy, B.z * dz));
     float dq = fmaf(dx, qx, fmaf(dy, qy, dz * qz));
-    float a5 = dq * ri5;
-    acc.w = acc.w - mr;
-    acc.w = fmaf(C.z, ri3, acc.w);
-    acc.w = fmaf(0.5f, a5, acc.w);
-    float u = fmaf(-2.5f, a5, mr);
-    float s = fmaf(C.w, ri5, u * ri2);
+    float w = dq * ri2;
+    float p = fmaf(fmaf(0.5f, w, C.z), ri2, -A.w);
+    acc.w = fmaf(p, ri, acc.w);
+    float g = fmaf(fmaf(-2.5f, w, C.w), ri2, A.w);
+    float s = g * ri3;
     acc.x = fmaf(s, dx, fmaf(qx, ri5, acc.x));
     acc.y = fmaf(s, dy, fmaf(qy, ri5, acc.y));
     acc.z = fmaf(s, dz, fmaf(qz, ri5, acc.z));
