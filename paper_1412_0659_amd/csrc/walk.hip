@@ -212,17 +212,23 @@ template <bool kIsPc, bool kEps0>
 __device__ __forceinline__ void eval_chunk(Phase &ph, uint32_t n, const WalkLds &L, float eps2) {
     const uint32_t r = ph.r;
     const uint32_t full = n / r, rem = n - full * r;
-    uint32_t k = ph.slice;
     uint32_t j = 0;
-    for (; j + 1u < full; j += 2u, k += 2u * r) {  // two sources per trip
-        if (kIsPc) {
-            pc_term(ph.tgt, L.stage[0][k], L.stage[1][k], L.stage[2][k], eps2, ph.acc);
-            pc_term(ph.tgt, L.stage[0][k + r], L.stage[1][k + r], L.stage[2][k + r], eps2, ph.acc);
-        } else {
-            pp_term<kEps0>(ph.tgt, L.stage[0][k], eps2, ph.acc);
-            pp_term<kEps0>(ph.tgt, L.stage[0][k + r], eps2, ph.acc);
+    {
+        // one induction variable: the lane's source record in stage[0]
+        // (stage[1], stage[2] follow at fixed offsets)
+        const float4 *src = &L.stage[0][ph.slice];
+        constexpr uint32_t kRow = kChunk + 1;
+        for (; j + 1u < full; j += 2u, src += 2u * r) {  // two sources per trip
+            if (kIsPc) {
+                pc_term(ph.tgt, src[0], src[kRow], src[2 * kRow], eps2, ph.acc);
+                pc_term(ph.tgt, src[r], src[r + kRow], src[r + 2 * kRow], eps2, ph.acc);
+            } else {
+                pp_term<kEps0>(ph.tgt, src[0], eps2, ph.acc);
+                pp_term<kEps0>(ph.tgt, src[r], eps2, ph.acc);
+            }
         }
     }
+    uint32_t k = ph.slice + j * r;
     if (j < full) {
         if (kIsPc) pc_term(ph.tgt, L.stage[0][k], L.stage[1][k], L.stage[2][k], eps2, ph.acc);
         else pp_term<kEps0>(ph.tgt, L.stage[0][k], eps2, ph.acc);
