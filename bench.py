@@ -36,10 +36,10 @@ def paper_flops(n_pp, n_pc):
 
 # Flops our kernel executes per interaction, counted in the gfx950 assembly
 # of the walk's evaluation loops (an FMA as 2, v_rsq_f32 as 4 like the
-# paper): p-p 6 FMA + 7 mul/add/sub + rsq = 23; p-c 22 FMA + 12 mul/sub
-# + rsq = 60 (the paper counts 65 for its p-c term).
+# paper): p-p 6 FMA + 7 mul/add/sub + rsq = 23; p-c 22 FMA + 11 mul/sub
+# + rsq = 59 (the paper counts 65 for its p-c term).
 KERNEL_FLOPS_PP = 23
-KERNEL_FLOPS_PC = 60
+KERNEL_FLOPS_PC = 59
 
 
 def walk_source_hash():

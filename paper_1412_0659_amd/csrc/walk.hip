@@ -35,18 +35,17 @@ __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v);
 // One particle-cell term, Eq. (1)-(2) with r^2 -> r^2 + eps^2.
 // A = (com x, y, z, M); B = (-3 Qxx, -3 Qyy, -3 Qzz, -3 Qxy);
 // C = (-3 Qxz, -3 Qyz, tr Q / 2, -3 tr Q / 2).  With q = -3 Q d and
-// w = d.q / r^2, in nested form (35 VALU operations and one rsq):
+// w = d.q / r^2, in nested form (33 VALU operations and one rsq):
 //   phi += -M/r + (tr/2)/r^3 + (1/2) d.q / r^5 = [-M + (tr/2 + w/2) / r^2] / r
 //   a   += d [M/r^3 - (3/2) tr/r^5 - (5/2) d.q / r^7] + q / r^5
-//        = d [M + (-3 tr/2 - 5 w/2) / r^2] / r^3 + q / r^5
+//        = (q + h d) / r^5,  h = M r^2 - 3 tr/2 - 5 w/2
 __device__ __forceinline__ void pc_term(const float4 &T, const float4 &A, const float4 &B,
                                         const float4 &C, float eps2, float4 &acc) {
     float dx = A.x - T.x, dy = A.y - T.y, dz = A.z - T.z;
     float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
     float ri = rsq(r2);
     float ri2 = ri * ri;
-    float ri3 = ri * ri2;
-    float ri5 = ri3 * ri2;
+    float ri5 = (ri2 * ri2) * ri;
     float qx = fmaf(B.x, dx, fmaf(B.w, dy, C.x * dz));
     float qy = fmaf(B.w, dx, fmaf(B.y, dy, C.y * dz));
     float qz = fmaf(C.x, dx, fmaf(C.y, dy, B.z * dz));
@@ -54,11 +53,10 @@ __device__ __forceinline__ void pc_term(const float4 &T, const float4 &A, const 
     float w = dq * ri2;
     float p = fmaf(fmaf(0.5f, w, C.z), ri2, -A.w);
     acc.w = fmaf(p, ri, acc.w);
-    float g = fmaf(fmaf(-2.5f, w, C.w), ri2, A.w);
-    float s = g * ri3;
-    acc.x = fmaf(s, dx, fmaf(qx, ri5, acc.x));
-    acc.y = fmaf(s, dy, fmaf(qy, ri5, acc.y));
-    acc.z = fmaf(s, dz, fmaf(qz, ri5, acc.z));
+    float h = fmaf(A.w, r2, fmaf(-2.5f, w, C.w));
+    acc.x = fmaf(ri5, fmaf(h, dx, qx), acc.x);
+    acc.y = fmaf(ri5, fmaf(h, dy, qy), acc.y);
+    acc.z = fmaf(ri5, fmaf(h, dz, qz), acc.z);
 }
 
 // One particle-particle term (a point mass P.w at P.xyz).
@@ -287,10 +285,12 @@ __device__ void walk_group(const WalkArgs &a, uint32_t g, uint32_t lane, WalkLds
     }
 
     // the null source of the FP32 staging area (rewritten by every flush: in
-    // the FP16 walk the pair records share that area)
+    // the FP16 walk the pair records share that area): massless and far
+    // enough that 1/r^5 underflows to zero while r^2 stays finite, so every
+    // product in its terms is an exact zero (M r^2 = 0 * inf would be NaN)
     auto put_null = [&]() {
         if (lane == 0) {
-            L.stage[0][kNull] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+            L.stage[0][kNull] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
             L.stage[1][kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
             L.stage[2][kNull] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
