@@ -6,8 +6,9 @@
 //
 // The kinds compared are those of the walk's particle-cell term: FP32 FMA
 // with all operands in VGPRs, FP32 FMA reading an SGPR, packed FP16 FMA,
-// mixed FP16/FP32 FMA (the FP16 far field's FP32 accumulation) and the
-// reciprocal square roots.  Measurement only; not part of the library.
+// mixed FP16/FP32 FMA (the FP16 far field's FP32 accumulation), the
+// reciprocal square roots, and single encodings of FMA, multiply and add.
+// Measurement only; not part of the library.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -90,6 +91,33 @@ __global__ __launch_bounds__(256) void k_rsq_f16(float *out, float a, float b) {
     out[blockIdx.x * 256 + threadIdx.x] = s;
 }
 
+// One instruction form per kernel, written out so the encoding is fixed:
+// VOP2 (4 bytes) against VOP3 (8 bytes), and the operand kinds of VOP2
+// (an SGPR, an inline constant, a 32-bit literal) that the walk's terms use.
+#define ASM_KERNEL(NAME, INSTR, ...)                                               \
+    __global__ __launch_bounds__(256) void NAME(float *out, float a, float b) {   \
+        float x[8], y[8];                                                        \
+        for (int i = 0; i < 8; ++i) {                                            \
+            x[i] = threadIdx.x * 1e-3f + i;                                      \
+            y[i] = a + i * 1e-4f * threadIdx.x;                                  \
+        }                                                                        \
+        for (int it = 0; it < kIt; ++it)                                         \
+            _Pragma("unroll") for (int i = 0; i < 8; ++i)                        \
+                asm volatile(INSTR : "+v"(x[i]) : __VA_ARGS__);                  \
+        float s = 0.f;                                                           \
+        for (int i = 0; i < 8; ++i) s += x[i];                                   \
+        out[blockIdx.x * 256 + threadIdx.x] = s;                                 \
+    }
+
+ASM_KERNEL(k_fmac_vop2, "v_fmac_f32_e32 %0, %1, %2", "v"(y[i]), "v"(y[(i + 3) & 7]))
+ASM_KERNEL(k_fma_vop3, "v_fma_f32 %0, %1, %2, %0", "v"(y[i]), "v"(y[(i + 3) & 7]))
+ASM_KERNEL(k_fma_vop3_neg, "v_fma_f32 %0, %1, %2, -%0", "v"(y[i]), "v"(y[(i + 3) & 7]))
+ASM_KERNEL(k_fmac_vop2_sgpr, "v_fmac_f32_e32 %0, %1, %2", "s"(a), "v"(y[i]))
+ASM_KERNEL(k_fmac_vop2_inline, "v_fmac_f32_e32 %0, 0.5, %1", "v"(y[i]))
+ASM_KERNEL(k_fmac_vop2_literal, "v_fmac_f32_e32 %0, 0x3f7fbe77, %1", "v"(y[i]))
+ASM_KERNEL(k_mul_vop2, "v_mul_f32_e32 %0, %1, %0", "v"(y[i]))
+ASM_KERNEL(k_add_u32_vop2_sgpr, "v_add_u32_e32 %0, %1, %0", "s"(a))
+
 typedef void (*Kern)(float *, float, float);
 
 static double rate(Kern k, float *d, int nb) {
@@ -123,7 +151,11 @@ int main() {
         const char *name;
         Kern k;
     } ks[] = {{"fma_f32_vgpr", k_f32_vgpr}, {"fma_f32_sgpr", k_f32_sgpr}, {"pk_fma_f16", k_pk_f16},
-              {"fma_mix_f32", k_mix},      {"rsq_f32", k_rsq_f32},      {"rsq_f16", k_rsq_f16}};
+              {"fma_mix_f32", k_mix},      {"rsq_f32", k_rsq_f32},      {"rsq_f16", k_rsq_f16},
+              {"fmac_vop2", k_fmac_vop2},  {"fma_vop3", k_fma_vop3},    {"fma_vop3_neg", k_fma_vop3_neg},
+              {"fmac_vop2_sgpr", k_fmac_vop2_sgpr}, {"fmac_vop2_inline", k_fmac_vop2_inline},
+              {"fmac_vop2_literal", k_fmac_vop2_literal}, {"mul_vop2", k_mul_vop2},
+              {"add_u32_vop2_sgpr", k_add_u32_vop2_sgpr}};
     printf("{\"unit\": \"wave64 instructions per cycle per SIMD at 2.4 GHz\", \"cus\": %d", cus);
     for (const auto &e : ks) printf(", \"%s\": %.3f", e.name, rate(e.k, d, nb));
     printf("}\n");
