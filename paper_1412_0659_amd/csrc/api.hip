@@ -287,7 +287,7 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
          dalloc(&q.prefix, nc, err) && dalloc(&q.level, nc, err) && dalloc(&q.begin, nc, err) &&
          dalloc(&q.count, nc, err) && dalloc(&q.child0, nc, err) && dalloc(&q.nchild, nc, err) &&
          dalloc(&q.parent, nc, err) && dalloc(&q.ls, kLsSize, err) &&
-         dalloc(&q.part, kGrid + 1, err) && dalloc(&q.M, nc, err) && dalloc(&q.S, 3 * nc, err) &&
+         dalloc(&q.part, kBuildGrid + 1, err) && dalloc(&q.M, nc, err) && dalloc(&q.S, 3 * nc, err) &&
          dalloc(&q.com, 3 * nc, err) && dalloc(&q.Q, 6 * nc, err) && dalloc(&q.wA, nc, err) &&
          dalloc(&q.wN, nc, err) && dalloc(&q.P0, nc, err) && dalloc(&q.P1, nc, err) &&
          dalloc(&q.P2, nc, err) && dalloc(&q.size, nc, err) && dalloc(&g.flag, n, err) &&

@@ -110,11 +110,11 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_count(Cells c,
     if (threadIdx.x == 0) c.part[blockIdx.x] = lds[0] + lds[1] + lds[2] + lds[3];
 }
 
-// exclusive scan of the kGrid block totals; sets the end of level l + 1
+// exclusive scan of the kBuildGrid block totals; sets the end of level l + 1
 __global__ __launch_bounds__(kBuildThreads) void k_build_scan(Cells c, int l, uint32_t cap,
                                                               uint32_t *status) {
     __shared__ uint32_t lds[4];
-    constexpr int per = kGrid / kBuildThreads;
+    constexpr int per = kBuildGrid / kBuildThreads;
     uint32_t v[per], s = 0;
 #pragma unroll
     for (int k = 0; k < per; ++k) {
@@ -200,11 +200,11 @@ void launch_build(bh_ctx *ctx, uint32_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_build_init, dim3(1), dim3(64), 0, st, c, n);
     uint32_t cap = (uint32_t)ctx->cap_cells;
     for (int l = 0; l < kLevels - 1; ++l) {
-        hipLaunchKernelGGL(k_build_count, dim3(kGrid), dim3(kBuildThreads), 0, st, c,
+        hipLaunchKernelGGL(k_build_count, dim3(kBuildGrid), dim3(kBuildThreads), 0, st, c,
                            (const uint64_t *)ctx->sort.key[0], l, (uint32_t)ctx->p.nleaf);
         hipLaunchKernelGGL(k_build_scan, dim3(1), dim3(kBuildThreads), 0, st, c, l, cap,
                            ctx->status);
-        hipLaunchKernelGGL(k_build_write, dim3(kGrid), dim3(kBuildThreads), 0, st, c,
+        hipLaunchKernelGGL(k_build_write, dim3(kBuildGrid), dim3(kBuildThreads), 0, st, c,
                            (const uint64_t *)ctx->sort.key[0], l, cap);
     }
 }
