@@ -305,8 +305,10 @@ int bh_set_box(bh_ctx *ctx, const float *lo, float side);
  * cost of slots [0, i) reaches j/p of the total, clamped so that no domain
  * holds more than C = floor(cap n / p) particles: cuts[j] in
  * [max(cuts[j-1], n - (p - j) C), min(cuts[j-1] + C, n)].  Domains may be
- * empty.  Synchronises s.  Errors: BH_EINVAL (p outside [1, n], cap < 1 or
- * C p < n), BH_ESTATE (no walk since the last build). */
+ * empty.  Computed on the device (costs, cuts and clamp), then copied to
+ * cuts; synchronises s.  Errors: BH_EINVAL (p outside [1, n], cap < 1 or
+ * C p < n), BH_ENOMEM (device scratch of 8 (n + p + 2) bytes), BH_ESTATE (no
+ * walk since the last build). */
 int bh_decompose(bh_ctx *ctx, int32_t p, float cap, int64_t *cuts, hipStream_t s);
 
 /* The same cut by the paper's two-level sampling (Sec. III.B.1), run on the

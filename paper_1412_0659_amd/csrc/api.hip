@@ -63,6 +63,7 @@ void free_all(bh_ctx *c) {
     Let &t = c->let;
     f(t.wA); f(t.P0); f(t.P1); f(t.P2); f(t.xyzm); f(t.wN); f(t.origin);
     f(t.cmark); f(t.omark); f(t.cscan); f(t.pmark); f(t.pscan); f(t.spart); f(t.word);
+    f(c->cut.S); f(c->cut.cuts);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
 }
@@ -135,6 +136,12 @@ int check_n(bh_ctx *c, int64_t n) {
     if (n <= 0) return fail(c, BH_EINVAL, "n must be positive");
     if (n > c->nmax) return fail(c, BH_ECAPACITY, "n exceeds the context capacity");
     return BH_OK;
+}
+
+// C = floor(cap n / p), at most n (a larger C clamps nothing more)
+int64_t cap_count(float cap, int64_t n, int32_t p) {
+    const double v = std::floor((double)cap * (double)n / (double)p);
+    return v >= (double)n ? n : (int64_t)v;
 }
 
 // Per sorted particle: 23 npp + 65 npc of its group's last walk (host).
@@ -660,43 +667,16 @@ int bh_decompose(bh_ctx *c, int32_t p, float cap, int64_t *cuts, hipStream_t s) 
     const int64_t n = c->n;
     if (p < 1 || p > n) return fail(c, BH_EINVAL, "p must be in [1, n]");
     if (!std::isfinite(cap) || !(cap >= 1.f)) return fail(c, BH_EINVAL, "cap must be >= 1");
-    const int64_t C = (int64_t)std::floor((double)cap * (double)n / (double)p);
+    const int64_t C = cap_count(cap, n, p);
     if (C * (int64_t)p < n) return fail(c, BH_EINVAL, "cap * n / p cannot hold n particles");
-    BH_HIP(c, hipStreamSynchronize(s));
-    uint32_t ng = 0;
-    BH_HIP(c, hipMemcpy(&ng, c->groups.count_dev, sizeof(ng), hipMemcpyDeviceToHost));
     std::string err;
-    uint32_t *hb = new (std::nothrow) uint32_t[3 * (size_t)ng + 1];
-    if (!hb) return fail(c, BH_ENOMEM, "host allocation");
-    uint32_t *npp = hb + ng + 1, *npc = npp + ng;
-    hipError_t e = hipMemcpy(hb, c->groups.begin, 4 * ((size_t)ng + 1), hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(npp, c->groups.npp, 4 * (size_t)ng, hipMemcpyDeviceToHost);
-    if (e == hipSuccess) e = hipMemcpy(npc, c->groups.npc, 4 * (size_t)ng, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) {
-        delete[] hb;
-        BH_HIP(c, e);
-    }
-    // running cost S_i of the particles before sorted slot i; cut j is the
-    // first i with S_i p >= W j (exact in 128-bit integers)
-    __int128 W = 0;
-    for (uint32_t g = 0; g < ng; ++g)
-        W += (__int128)(hb[g + 1] - hb[g]) * (23 * (__int128)npp[g] + 65 * (__int128)npc[g]);
-    cuts[0] = 0;
-    __int128 S = 0;
-    int32_t j = 1;
-    for (uint32_t g = 0; g < ng && j < p; ++g) {
-        const __int128 w = 23 * (__int128)npp[g] + 65 * (__int128)npc[g];
-        for (uint32_t i = hb[g]; i < hb[g + 1] && j < p; ++i) {
-            while (j < p && S * p >= W * j) cuts[j++] = i;
-            S += w;
-        }
-    }
-    while (j < p) {
-        if (S * p >= W * j) cuts[j] = n;
-        ++j;
-    }
-    delete[] hb;
-    clamp_cuts(cuts, p, n, C);
+    if (!grow(&c->cut.S, c->cut.S_cap, n + 1, err) ||
+        !grow(&c->cut.cuts, c->cut.cuts_cap, (int64_t)p + 1, err))
+        return fail(c, BH_ENOMEM, err);
+    launch_cut(c, p, C, c->cut.S, c->cut.cuts, s);
+    BH_HIP(c, hipGetLastError());
+    BH_HIP(c, hipMemcpyAsync(cuts, c->cut.cuts, 8 * ((size_t)p + 1), hipMemcpyDeviceToHost, s));
+    BH_HIP(c, hipStreamSynchronize(s));
     return check_status(c);
 }
 
@@ -712,7 +692,7 @@ int bh_decompose_sampled(bh_ctx *c, int32_t px, int32_t py, int32_t m1, int32_t 
     if (m1 < 1 || m2 < 1) return fail(c, BH_EINVAL, "sample counts must be >= 1");
     const int32_t p = px * py;
     if (!std::isfinite(cap) || !(cap >= 1.f)) return fail(c, BH_EINVAL, "cap must be >= 1");
-    const int64_t C = (int64_t)std::floor((double)cap * (double)n / (double)p);
+    const int64_t C = cap_count(cap, n, p);
     if (C * (int64_t)p < n) return fail(c, BH_EINVAL, "cap * n / p cannot hold n particles");
     BH_HIP(c, hipStreamSynchronize(s));
     std::vector<int64_t> cost;

@@ -103,6 +103,13 @@ struct Let {
     uint32_t *word = nullptr;   // [1] a terminal boundary cell was opened
 };
 
+// Device buffers of the domain cut: group-start costs and the cuts.
+struct Cut {
+    uint64_t *S = nullptr;  // [n + 1]
+    int64_t *cuts = nullptr;  // [p + 1]
+    int64_t S_cap = 0, cuts_cap = 0;
+};
+
 struct Sort {
     uint64_t *key[2];
     uint32_t *idx[2];
@@ -146,6 +153,7 @@ struct bh_ctx {
 
     bh::Boundary bnd{};
     bh::Let let{};
+    bh::Cut cut{};
 
     bool built = false, have_acc = false;
     bool counts_valid = false;  // npp / npc / totals describe a walk of the current groups
@@ -248,6 +256,7 @@ void launch_totals(bh_ctx *c, uint32_t n, hipStream_t st);
 void launch_count_leaves(bh_ctx *c, hipStream_t st);
 void launch_diagnostics(bh_ctx *c, hipStream_t st);  // result at diag + kDiagBlocks * kDiagN
 void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
+void launch_cut(bh_ctx *c, int32_t p, int64_t C, uint64_t *S, int64_t *cuts, hipStream_t st);
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
