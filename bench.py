@@ -436,8 +436,9 @@ def main(argv=None):
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the "
-              "library implements the single-GPU path (the domain decomposition and "
-              "tree exchange across GPUs are not implemented)", file=sys.stderr)
+              "library runs on one GPU (several spatial domains run as contexts on that "
+              "device, --domains; the exchange between GPUs is not implemented)",
+              file=sys.stderr)
         return 2
 
     import numpy as np
