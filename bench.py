@@ -25,7 +25,8 @@ if ROOT not in sys.path:
 FLOPS_PP = 23
 FLOPS_PC = 65
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CUs x 2.4 GHz x 256 flop/clk)
-WALK_SOURCE = os.path.join(ROOT, "paper_1412_0659_amd", "csrc", "walk.hip")
+WALK_SOURCES = [os.path.join(ROOT, "paper_1412_0659_amd", "csrc", f)
+                for f in ("walk.hip", "walk_common.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_disk_halo_13m_traffic.json")
 
 
@@ -43,8 +44,12 @@ KERNEL_FLOPS_PC = 59
 
 
 def walk_source_hash():
-    with open(WALK_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the walk kernel's sources (the evaluation and the traversal)."""
+    h = hashlib.sha256()
+    for path in WALK_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def load_traffic():

@@ -28,7 +28,7 @@
 namespace bh {
 
 constexpr int kRing = 256;   // LDS window of the range stack (TreeView::ring <= kRing)
-constexpr int kPcCap = 256;  // particle-cell index list
+constexpr int kPcCap = 768;  // particle-cell index list
 constexpr int kPcFlush = kPcCap - 64;
 constexpr int kPpCap = 512;  // particle-particle index list
 constexpr int kChunk = 64;   // sources staged per evaluation round
