@@ -144,6 +144,25 @@ def test_sampled_decompose_bit_exact(oracle, curve, px, py, m1, m2, cap):
     assert np.array_equal(gcuts, cuts) and np.array_equal(gbounds, bounds)
 
 
+@pytest.mark.parametrize("n,p,cap", [(5000, 5000, 1.0), (5000, 4500, 2.0), (5000, 4097, 2.0)])
+def test_decompose_many_domains(oracle, n, p, cap):
+    """More cuts than one LDS tile of the clamp (4096), up to one particle per
+    domain: the same cuts as the oracle's."""
+    pos, mass = _disk(n)
+    theta, eps = 0.4, 0.01
+    g = oracle.build_tree(pos, mass)
+    _, _, npp, npc = oracle.walk(g, theta, eps)
+    cost = LT.particle_cost(g.n, g.gbeg, g.gcnt, npp, npc)
+    cuts = LT.decompose(cost, p, cap)
+    t = gpu_tree(pos, mass)
+    gpu_force(t, theta, eps)
+    gcuts = t.decompose(p, cap)
+    print(f"  n={n} p={p} cap={cap}: {int(np.sum(np.diff(gcuts) == 0))} empty domains", flush=True)
+    assert np.array_equal(gcuts, cuts)
+    if p == n:
+        assert np.array_equal(gcuts, np.arange(n + 1))
+
+
 def test_decompose_errors():
     from paper_1412_0659_amd import BhError
     pos, mass = _disk(3000)
