@@ -53,7 +53,7 @@ void free_all(bh_ctx *c) {
     f(c->sort.counts); f(c->sort.scan_part);
     Cells &q = c->cells;
     f(q.prefix); f(q.level); f(q.begin); f(q.count); f(q.child0); f(q.nchild); f(q.parent);
-    f(q.ls); f(q.part); f(q.M); f(q.S); f(q.com); f(q.Q); f(q.wA); f(q.wN); f(q.P0); f(q.P1);
+    f(q.ls); f(q.part); f(q.lbt); f(q.M); f(q.S); f(q.com); f(q.Q); f(q.wA); f(q.wN); f(q.P0); f(q.P1);
     f(q.P2); f(q.size);
     Groups &g = c->groups;
     f(g.flag); f(g.scan); f(g.begin); f(g.count_dev); f(g.box); f(g.npp); f(g.npc);
@@ -294,7 +294,8 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
          dalloc(&q.prefix, nc, err) && dalloc(&q.level, nc, err) && dalloc(&q.begin, nc, err) &&
          dalloc(&q.count, nc, err) && dalloc(&q.child0, nc, err) && dalloc(&q.nchild, nc, err) &&
          dalloc(&q.parent, nc, err) && dalloc(&q.ls, kLsSize, err) &&
-         dalloc(&q.part, kBuildGrid + 1, err) && dalloc(&q.M, nc, err) && dalloc(&q.S, 3 * nc, err) &&
+         dalloc(&q.part, kBuildGrid + 1, err) &&
+         dalloc(&q.lbt, ((size_t)1 << (3 * kTableLevel)) + 1, err) && dalloc(&q.M, nc, err) && dalloc(&q.S, 3 * nc, err) &&
          dalloc(&q.com, 3 * nc, err) && dalloc(&q.Q, 6 * nc, err) && dalloc(&q.wA, nc, err) &&
          dalloc(&q.wN, nc, err) && dalloc(&q.P0, nc, err) && dalloc(&q.P1, nc, err) &&
          dalloc(&q.P2, nc, err) && dalloc(&q.size, nc, err) && dalloc(&g.flag, n, err) &&

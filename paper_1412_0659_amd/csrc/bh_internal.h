@@ -18,6 +18,7 @@ constexpr int kLevels = 22;             // levels 0..21
 constexpr int kLsSize = 24;             // level_start entries (23 used)
 constexpr int kGrid = 1024;             // fixed grid of the per-level moment, box and flag kernels
 constexpr int kBuildGrid = 2048;        // grid of the octree level kernels: 8 waves per SIMD
+constexpr int kTableLevel = 6;          // the build looks up the child bounds of levels < 6
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr int kStackMax = 1408;         // walk stack bound: 21 levels x 64 ranges + root
@@ -44,6 +45,7 @@ struct Cells {
     uint32_t *level, *begin, *count, *child0, *nchild, *parent;
     uint32_t *ls;      // [kLsSize] level_start on the device
     uint32_t *part;    // [kBuildGrid + 1] per-block partials of the level scans
+    uint32_t *lbt;     // [8^kTableLevel + 1] first sorted slot of every level-kTableLevel prefix
     // FP64 moments of the upward pass
     double *M, *S, *com, *Q;  // [c], [c][3], [c][3], [c][6]
     // records read by the walk

@@ -8,7 +8,12 @@
 // search for the key bound (8 P + d) << 3 (20 - l) inside the cell's range.
 // Each level takes three launches over a fixed grid that reads the level's
 // cell range from device memory (count children / scan block totals / write
-// children), so the build never waits on the host.
+// children), so the build never waits on the host.  On the top levels the
+// searches are replaced by a table: for every key prefix q of level
+// kTableLevel, lbt[q] is the first sorted slot whose key is >= q shifted to a
+// full key (a lower bound over all keys, so inside a cell it is exactly the
+// bound the search would find); one launch of 8^kTableLevel independent
+// searches fills it per build.
 #include "bh_internal.h"
 #include "wave.h"
 
@@ -33,12 +38,19 @@ __device__ __forceinline__ uint32_t key_lower_bound(const uint64_t *__restrict__
 // searches in lock step over the whole range, so their loads overlap
 // instead of waiting on each other; otherwise the searches are chained,
 // each starting at the previous bound (fewer loads).
-__device__ __forceinline__ void child_bounds(const uint64_t *__restrict__ key, uint64_t P,
+__device__ __forceinline__ void child_bounds(const uint64_t *__restrict__ key,
+                                             const uint32_t *__restrict__ lbt, uint64_t P,
                                              uint32_t b, uint32_t e, int l, bool few,
                                              uint32_t bnd[9]) {
     uint32_t shift = 3u * (kKeyBits - 1 - l);
     bnd[0] = b;
     bnd[8] = e;
+    if (l < kTableLevel) {  // children on a level <= kTableLevel: look the bounds up
+        const uint32_t up = 3u * (uint32_t)(kTableLevel - 1 - l);
+#pragma unroll
+        for (uint32_t d = 1; d < 8; ++d) bnd[d] = lbt[((P << 3) | d) << up];
+        return;
+    }
     if (few && e - b >= 256u) {
         uint32_t base[8];
 #pragma unroll
@@ -97,7 +109,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_count(Cells c,
         if (cnt > nleaf) {
             uint32_t bnd[9];
             uint32_t b = c.begin[i];
-            child_bounds(key, c.prefix[i], b, b + cnt, l, few, bnd);
+            child_bounds(key, c.lbt, c.prefix[i], b, b + cnt, l, few, bnd);
 #pragma unroll
             for (int d = 0; d < 8; ++d) nch += bnd[d + 1] > bnd[d];
         }
@@ -173,7 +185,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_write(Cells c,
             uint32_t b = c.begin[i];
             uint64_t P = c.prefix[i];
             uint32_t bnd[9];
-            child_bounds(key, P, b, b + c.count[i], l, few, bnd);
+            child_bounds(key, c.lbt, P, b, b + c.count[i], l, few, bnd);
             for (uint32_t d = 0; d < 8; ++d) {
                 if (bnd[d + 1] > bnd[d]) {
                     if (ch < cap) {
@@ -195,8 +207,22 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_write(Cells c,
     }
 }
 
+// lbt[q] for q in [0, 8^kTableLevel]: the first of the n sorted keys that is
+// >= q << 3 (21 - kTableLevel); lbt[8^kTableLevel] = n
+__global__ __launch_bounds__(256) void k_lb_table(const uint64_t *__restrict__ key, uint32_t n,
+                                                  uint32_t *__restrict__ lbt) {
+    constexpr uint32_t kQ = 1u << (3 * kTableLevel);
+    const uint32_t q = blockIdx.x * 256u + threadIdx.x;
+    if (q > kQ) return;
+    lbt[q] = q == kQ ? n
+                     : key_lower_bound(key, 0u, n, (uint64_t)q << (3 * (kKeyBits - kTableLevel)));
+}
+
 void launch_build(bh_ctx *ctx, uint32_t n, hipStream_t st) {
     Cells &c = ctx->cells;
+    constexpr uint32_t kQ = 1u << (3 * kTableLevel);
+    hipLaunchKernelGGL(k_lb_table, dim3((kQ + 1 + 255) / 256), dim3(256), 0, st,
+                       (const uint64_t *)ctx->sort.key[0], n, c.lbt);
     hipLaunchKernelGGL(k_build_init, dim3(1), dim3(64), 0, st, c, n);
     uint32_t cap = (uint32_t)ctx->cap_cells;
     for (int l = 0; l < kLevels - 1; ++l) {
