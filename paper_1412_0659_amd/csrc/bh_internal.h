@@ -18,7 +18,7 @@ constexpr int kLevels = 22;             // levels 0..21
 constexpr int kLsSize = 24;             // level_start entries (23 used)
 constexpr int kGrid = 1024;             // fixed grid of the per-level moment, box and flag kernels
 constexpr int kBuildGrid = 2048;        // grid of the octree level kernels: 8 waves per SIMD
-constexpr int kTableLevel = 6;          // the build looks up the child bounds of levels < 6
+constexpr int kTableLevel = 7;          // the build looks up the child bounds of levels < 7
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr int kStackMax = 1408;         // walk stack bound: 21 levels x 64 ranges + root
