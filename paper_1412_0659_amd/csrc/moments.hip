@@ -19,6 +19,12 @@
 
 namespace bh {
 
+// Leaves of at most kStage particles are read once into registers (the loads
+// issue together instead of one trip at a time) and summed from there; larger
+// leaves (nleaf > kStage, or the deepest level) read their particles twice.
+// The sums run in the same order either way.
+constexpr uint32_t kStage = 16;
+
 __global__ __launch_bounds__(256) void k_moments_leaf(Cells c, const float *__restrict__ x,
                                                       const float *__restrict__ y,
                                                       const float *__restrict__ z,
@@ -26,26 +32,61 @@ __global__ __launch_bounds__(256) void k_moments_leaf(Cells c, const float *__re
     uint32_t nc = c.ls[kLevels];
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) {
         if (c.nchild[i] != 0) continue;
-        uint32_t b = c.begin[i], e = b + c.count[i];
+        const uint32_t b = c.begin[i], cnt = c.count[i], e = b + cnt;
         double mm = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (uint32_t j = b; j < e; ++j) {
-            double mj = m[j];
-            mm = mm + mj;
-            s0 = s0 + mj * (double)x[j];
-            s1 = s1 + mj * (double)y[j];
-            s2 = s2 + mj * (double)z[j];
-        }
-        double c0 = s0 / mm, c1 = s1 / mm, c2 = s2 / mm;
         double q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0;
-        for (uint32_t j = b; j < e; ++j) {
-            double mj = m[j];
-            double d0 = (double)x[j] - c0, d1 = (double)y[j] - c1, d2 = (double)z[j] - c2;
-            q0 = q0 + (mj * d0) * d0;
-            q1 = q1 + (mj * d1) * d1;
-            q2 = q2 + (mj * d2) * d2;
-            q3 = q3 + (mj * d0) * d1;
-            q4 = q4 + (mj * d0) * d2;
-            q5 = q5 + (mj * d1) * d2;
+        double c0, c1, c2;
+        if (cnt <= kStage) {
+            float px[kStage], py[kStage], pz[kStage], pm[kStage];
+#pragma unroll
+            for (uint32_t k = 0; k < kStage; ++k) {
+                const uint32_t j = k < cnt ? b + k : b;
+                px[k] = x[j]; py[k] = y[j]; pz[k] = z[j]; pm[k] = m[j];
+            }
+#pragma unroll
+            for (uint32_t k = 0; k < kStage; ++k) {
+                if (k < cnt) {
+                    const double mj = pm[k];
+                    mm = mm + mj;
+                    s0 = s0 + mj * (double)px[k];
+                    s1 = s1 + mj * (double)py[k];
+                    s2 = s2 + mj * (double)pz[k];
+                }
+            }
+            c0 = s0 / mm; c1 = s1 / mm; c2 = s2 / mm;
+#pragma unroll
+            for (uint32_t k = 0; k < kStage; ++k) {
+                if (k < cnt) {
+                    const double mj = pm[k];
+                    const double d0 = (double)px[k] - c0, d1 = (double)py[k] - c1,
+                                 d2 = (double)pz[k] - c2;
+                    q0 = q0 + (mj * d0) * d0;
+                    q1 = q1 + (mj * d1) * d1;
+                    q2 = q2 + (mj * d2) * d2;
+                    q3 = q3 + (mj * d0) * d1;
+                    q4 = q4 + (mj * d0) * d2;
+                    q5 = q5 + (mj * d1) * d2;
+                }
+            }
+        } else {
+            for (uint32_t j = b; j < e; ++j) {
+                double mj = m[j];
+                mm = mm + mj;
+                s0 = s0 + mj * (double)x[j];
+                s1 = s1 + mj * (double)y[j];
+                s2 = s2 + mj * (double)z[j];
+            }
+            c0 = s0 / mm; c1 = s1 / mm; c2 = s2 / mm;
+            for (uint32_t j = b; j < e; ++j) {
+                double mj = m[j];
+                double d0 = (double)x[j] - c0, d1 = (double)y[j] - c1, d2 = (double)z[j] - c2;
+                q0 = q0 + (mj * d0) * d0;
+                q1 = q1 + (mj * d1) * d1;
+                q2 = q2 + (mj * d2) * d2;
+                q3 = q3 + (mj * d0) * d1;
+                q4 = q4 + (mj * d0) * d2;
+                q5 = q5 + (mj * d1) * d2;
+            }
         }
         c.M[i] = mm;
         c.S[3 * i] = s0; c.S[3 * i + 1] = s1; c.S[3 * i + 2] = s2;
@@ -55,32 +96,47 @@ __global__ __launch_bounds__(256) void k_moments_leaf(Cells c, const float *__re
     }
 }
 
+// A parent reads the mass and first moments of its (at most eight) children
+// at once, then sums them in child order.
 __global__ __launch_bounds__(256) void k_moments_up(Cells c, int l) {
     uint32_t first = c.ls[l], last = c.ls[l + 1];
     for (uint32_t i = first + blockIdx.x * 256 + threadIdx.x; i < last;
          i += gridDim.x * 256) {
-        uint32_t nch = c.nchild[i];
+        const uint32_t nch = c.nchild[i];
         if (nch == 0) continue;
-        uint32_t k0 = c.child0[i], k1 = k0 + nch;
+        const uint32_t k0 = c.child0[i];
+        double cm[8], cs0[8], cs1[8], cs2[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+            const uint32_t j = k0 + (k < nch ? k : 0u);
+            cm[k] = c.M[j]; cs0[k] = c.S[3 * j]; cs1[k] = c.S[3 * j + 1]; cs2[k] = c.S[3 * j + 2];
+        }
         double mm = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (uint32_t k = k0; k < k1; ++k) {
-            mm = mm + c.M[k];
-            s0 = s0 + c.S[3 * k];
-            s1 = s1 + c.S[3 * k + 1];
-            s2 = s2 + c.S[3 * k + 2];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+            if (k < nch) {
+                mm = mm + cm[k];
+                s0 = s0 + cs0[k];
+                s1 = s1 + cs1[k];
+                s2 = s2 + cs2[k];
+            }
         }
         double c0 = s0 / mm, c1 = s1 / mm, c2 = s2 / mm;
         double q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0;
-        for (uint32_t k = k0; k < k1; ++k) {
-            double mk = c.M[k];
-            double d0 = c.com[3 * k] - c0, d1 = c.com[3 * k + 1] - c1, d2 = c.com[3 * k + 2] - c2;
-            const double *qk = c.Q + 6 * (size_t)k;
-            q0 = q0 + (qk[0] + (mk * d0) * d0);
-            q1 = q1 + (qk[1] + (mk * d1) * d1);
-            q2 = q2 + (qk[2] + (mk * d2) * d2);
-            q3 = q3 + (qk[3] + (mk * d0) * d1);
-            q4 = q4 + (qk[4] + (mk * d0) * d2);
-            q5 = q5 + (qk[5] + (mk * d1) * d2);
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+            if (k < nch) {
+                const uint32_t j = k0 + k;
+                const double mk = cm[k];
+                double d0 = c.com[3 * j] - c0, d1 = c.com[3 * j + 1] - c1, d2 = c.com[3 * j + 2] - c2;
+                const double *qk = c.Q + 6 * (size_t)j;
+                q0 = q0 + (qk[0] + (mk * d0) * d0);
+                q1 = q1 + (qk[1] + (mk * d1) * d1);
+                q2 = q2 + (qk[2] + (mk * d2) * d2);
+                q3 = q3 + (qk[3] + (mk * d0) * d1);
+                q4 = q4 + (qk[4] + (mk * d0) * d2);
+                q5 = q5 + (qk[5] + (mk * d1) * d2);
+            }
         }
         c.M[i] = mm;
         c.S[3 * i] = s0; c.S[3 * i + 1] = s1; c.S[3 * i + 2] = s2;
