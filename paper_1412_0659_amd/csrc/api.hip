@@ -2,6 +2,7 @@
 // launches for a build / force evaluation / leapfrog step, statistics and
 // array export.  Declarations and contracts are in include/bh.h.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -64,6 +65,7 @@ void free_all(bh_ctx *c) {
     f(t.wA); f(t.P0); f(t.P1); f(t.P2); f(t.xyzm); f(t.wN); f(t.origin);
     f(t.cmark); f(t.omark); f(t.cscan); f(t.pmark); f(t.pscan); f(t.spart); f(t.word);
     f(c->cut.S); f(c->cut.cuts);
+    if (c->hint_host) (void)hipHostFree(c->hint_host);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
 }
@@ -83,18 +85,43 @@ int check_status(bh_ctx *c) {
     return fail(c, BH_ECAPACITY, "cell or stack capacity exceeded");
 }
 
-void rebuild(bh_ctx *c, uint32_t n, hipStream_t s) {
+// Levels the grid kernels split: one past the deepest level of a recent tree
+// of the same particle set when one has been published (a tail kernel splits
+// any deeper level), else all of them.  The published copy is read without
+// waiting: its two build numbers agree only if it was read whole.
+int grid_levels(bh_ctx *c, bool fresh) {
+    if (c->forced_grid_levels >= 0) return std::min(c->forced_grid_levels, kLevels - 1);
+    if (fresh || !c->hint_host) return kLevels - 1;
+    const volatile uint32_t *h = c->hint_host;
+    const uint32_t last = h[1];
+    std::atomic_thread_fence(std::memory_order_acquire);
+    uint32_t ls[kLevels + 1];
+    for (int k = 0; k < kLevels + 1; ++k) ls[k] = h[2 + k];
+    std::atomic_thread_fence(std::memory_order_acquire);
+    const uint32_t first = h[0];
+    if (first != last || last < c->hint_gen_min || last > c->build_gen) return kLevels - 1;
+    int deepest = -1;
+    for (int l = 0; l < kLevels; ++l)
+        if (ls[l + 1] > ls[l]) deepest = l;
+    return deepest < 0 ? kLevels - 1 : std::min(kLevels - 1, deepest + 1);
+}
+
+// fresh: a new particle set (no earlier tree describes it)
+void rebuild(bh_ctx *c, uint32_t n, hipStream_t s, bool fresh) {
+    if (fresh) c->hint_gen_min = c->build_gen + 1;
+    const int L = grid_levels(c, fresh);
+    ++c->build_gen;
     (void)hipEventRecord(c->ev[0], s);
     launch_bbox(c, c->st[c->cur], n, s);
     launch_keys(c, c->st[c->cur], n, s);
     launch_radix_sort(c, n, s);
     launch_gather(c, n, s);
     (void)hipEventRecord(c->ev[1], s);
-    launch_build(c, n, s);
+    launch_build(c, n, s, L);
     launch_groups(c, n, s);
     launch_count_leaves(c, s);
     (void)hipEventRecord(c->ev[2], s);
-    launch_moments(c, s);
+    launch_moments(c, s, L);
     (void)hipEventRecord(c->ev[3], s);
     c->ev_rec[0] = c->ev_rec[1] = c->ev_rec[2] = c->ev_rec[3] = true;
     c->built = true;
@@ -284,6 +311,10 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
         // reach the spill / refill path with moderate trees
         const char *v = std::getenv("BH_WALK_SMALL_STACK");
         c->walk_small_stack = v && v[0] == '1';
+        // test hook: the number of levels the grid kernels split in every
+        // build (the single-workgroup tail splits the rest)
+        const char *g = std::getenv("BH_BUILD_GRID_LEVELS");
+        c->forced_grid_levels = g && g[0] ? std::atoi(g) : -1;
     }
     ok = ok && dalloc(&c->acc, n, err) && dalloc(&c->xyzm, n, err) &&
          dalloc(&c->spill, (size_t)c->walk_grid * kStackMax, err) && dalloc(&c->box, 8, err) &&
@@ -308,6 +339,19 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
              dalloc(&c->usort, n, err) && dalloc(&c->leafof, n, err);
     for (auto &e : c->ev)
         if (ok && hipEventCreate(&e) != hipSuccess) ok = false;
+    // pinned, device-visible copy of a recent build's level starts (zeroed: none yet)
+    // (coherent, so the device's stores reach host memory in the order fenced)
+    if (ok && hipHostMalloc((void **)&c->hint_host, (kLevels + 3) * sizeof(uint32_t),
+                            hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        c->hint_host = nullptr;
+        (void)hipGetLastError();
+        ok = false;
+    }
+    if (ok) std::memset(c->hint_host, 0, (kLevels + 3) * sizeof(uint32_t));
+    if (ok && hipHostGetDevicePointer((void **)&c->hint_dev, c->hint_host, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        ok = false;
+    }
     if (ok && hipMemset(c->status, 0, 4 * sizeof(uint32_t)) != hipSuccess) ok = false;
     if (!ok) {
         free_all(c);
@@ -339,7 +383,7 @@ int bh_set_state(bh_ctx *c, const float *pos, const float *vel, const float *mas
     c->n = n;
     c->cur = 0;
     launch_ingest(c, pos, vel, mass, (uint32_t)n, s);
-    rebuild(c, (uint32_t)n, s);
+    rebuild(c, (uint32_t)n, s, true);
     c->ev_rec[6] = c->ev_rec[7] = false;
     BH_HIP(c, hipGetLastError());
     return BH_OK;
@@ -366,7 +410,7 @@ int leapfrog_step(bh_ctx *c, float dt, float theta, float eps, hipStream_t s) {
     (void)hipEventRecord(c->ev[6], s);
     if (!c->have_acc || theta != c->acc_theta || eps != c->acc_eps) force(c, theta, eps, s);
     launch_kick_drift(c, 0.5f * dt, dt, n, s);
-    rebuild(c, n, s);
+    rebuild(c, n, s, false);
     force(c, theta, eps, s);
     launch_kick(c, 0.5f * dt, n, s);
     (void)hipEventRecord(c->ev[7], s);
@@ -603,7 +647,7 @@ int bh_load_state(bh_ctx *c, const void *src, int64_t n64, hipStream_t s) {
             p += n * sizeof(double);
         }
     }
-    rebuild(c, (uint32_t)n, s);
+    rebuild(c, (uint32_t)n, s, true);
     c->ev_rec[6] = c->ev_rec[7] = false;
     BH_HIP(c, hipGetLastError());
     return BH_OK;

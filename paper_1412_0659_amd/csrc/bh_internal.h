@@ -157,6 +157,14 @@ struct bh_ctx {
     bh::Let let{};
     bh::Cut cut{};
 
+    // level starts of a recent build, written by k_build_tail into pinned host
+    // memory: [0] build number (written first), [1] build number (written
+    // last), [2 ..] ls[0 .. kLevels]
+    uint32_t *hint_host = nullptr;
+    uint32_t *hint_dev = nullptr;  // the same memory as the device addresses it
+    uint32_t build_gen = 0;     // builds launched so far
+    uint32_t hint_gen_min = 1;  // first build of the current particle set
+
     bool built = false, have_acc = false;
     bool counts_valid = false;  // npp / npc / totals describe a walk of the current groups
     bool fixed_box = false;     // keys relative to a caller-given box (bh_set_box)
@@ -164,6 +172,7 @@ struct bh_ctx {
     float acc_theta = 0.f, acc_eps = 0.f;
     int walk_grid = 0;
     bool walk_small_stack = false;  // test hook: 128-entry LDS stack window
+    int forced_grid_levels = -1;    // test hook: levels split by the grid kernels
 
     // events: build start, after sort, after octree+groups, after moments,
     // walk start, walk end, step start, step end
@@ -206,11 +215,11 @@ void launch_exclusive_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32
                            hipStream_t st);
 
 // build.hip
-void launch_build(bh_ctx *c, uint32_t n, hipStream_t st);
+void launch_build(bh_ctx *c, uint32_t n, hipStream_t st, int grid_levels);
 void launch_groups(bh_ctx *c, uint32_t n, hipStream_t st);
 
 // moments.hip
-void launch_moments(bh_ctx *c, hipStream_t st);
+void launch_moments(bh_ctx *c, hipStream_t st, int grid_levels);
 void launch_walk_prep(bh_ctx *c, float theta, hipStream_t st);
 
 // let.hip: boundary trees and local essential trees (Sec. III.B.2); nc is

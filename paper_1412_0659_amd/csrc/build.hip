@@ -218,14 +218,111 @@ __global__ __launch_bounds__(256) void k_lb_table(const uint64_t *__restrict__ k
                      : key_lower_bound(key, 0u, n, (uint64_t)q << (3 * (kKeyBits - kTableLevel)));
 }
 
-void launch_build(bh_ctx *ctx, uint32_t n, hipStream_t st) {
+// Levels l0 .. 20 in one workgroup: the deep end of the tree, where a level
+// holds few cells (or none) and three launches per level would cost more
+// than the work.  Per level: each round of 1024 cells finds its children's
+// bounds, a block scan numbers the children in cell order, and the children
+// are written, exactly as the three grid kernels would.  Any level size is
+// handled (only more slowly), so the split between grid and tail levels
+// affects the time, never the tree.  Then publishes the level starts and the
+// build's number to the host (pinned memory, tagged before and after).
+constexpr int kTailThreads = 1024;
+
+__global__ __launch_bounds__(kTailThreads) void k_build_tail(Cells c,
+                                                             const uint64_t *__restrict__ key,
+                                                             int l0, uint32_t nleaf, uint32_t cap,
+                                                             uint32_t *status,
+                                                             volatile uint32_t *hint,
+                                                             uint32_t gen) {
+    __shared__ uint32_t wtot[kTailThreads / 64];
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t first = 0, last = 0;
+    if (l0 < kLevels - 1) {
+        first = c.ls[l0];
+        last = c.ls[l0 + 1];
+    }
+    for (int l = l0; l < kLevels - 1; ++l) {
+        const bool few = last - first < kFewCells;
+        uint32_t next = last;  // the next level is built at [last, next)
+        for (uint32_t base = first; base < last; base += kTailThreads) {
+            const uint32_t i = base + threadIdx.x;
+            uint32_t bnd[9];
+            uint32_t nch = 0, b = 0;
+            uint64_t P = 0;
+            if (i < last) {
+                const uint32_t cnt = c.count[i];
+                if (cnt > nleaf) {
+                    b = c.begin[i];
+                    P = c.prefix[i];
+                    child_bounds(key, c.lbt, P, b, b + cnt, l, few, bnd);
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) nch += bnd[d + 1] > bnd[d];
+                }
+                c.nchild[i] = nch;
+            }
+            const uint32_t inc = wave_incl_scan(nch, lane);
+            if (lane == 63) wtot[w] = inc;
+            __syncthreads();
+            uint32_t off = 0, tot = 0;
+            for (uint32_t k = 0; k < (uint32_t)(kTailThreads / 64); ++k) {
+                if (k < w) off += wtot[k];
+                tot += wtot[k];
+            }
+            __syncthreads();
+            if (i < last) {
+                if (nch > 0) {
+                    uint32_t ch = next + off + inc - nch;
+                    c.child0[i] = ch;
+                    for (uint32_t d = 0; d < 8; ++d) {
+                        if (bnd[d + 1] > bnd[d]) {
+                            if (ch < cap) {
+                                c.prefix[ch] = (P << 3) | d;
+                                c.level[ch] = (uint32_t)(l + 1);
+                                c.begin[ch] = bnd[d];
+                                c.count[ch] = bnd[d + 1] - bnd[d];
+                                c.child0[ch] = kNone;
+                                c.nchild[ch] = 0;
+                                c.parent[ch] = i;
+                            }
+                            ++ch;
+                        }
+                    }
+                } else {
+                    c.child0[i] = kNone;
+                }
+            }
+            next += tot;
+        }
+        if (next > cap) {
+            if (threadIdx.x == 0) atomicOr(status, kStOverflow);
+            next = cap;
+        }
+        if (threadIdx.x == 0) c.ls[l + 2] = next;
+        __syncthreads();  // the new level's cells are read by the whole block next
+        first = last;
+        last = next;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        hint[0] = gen;
+        __threadfence_system();
+        for (int k = 0; k < kLevels + 1; ++k) hint[2 + k] = c.ls[k];
+        __threadfence_system();
+        hint[1] = gen;
+    }
+}
+
+// Levels 0 .. grid_levels - 1 are split by the grid kernels, the rest by
+// k_build_tail.
+void launch_build(bh_ctx *ctx, uint32_t n, hipStream_t st, int grid_levels) {
     Cells &c = ctx->cells;
     constexpr uint32_t kQ = 1u << (3 * kTableLevel);
     hipLaunchKernelGGL(k_lb_table, dim3((kQ + 1 + 255) / 256), dim3(256), 0, st,
                        (const uint64_t *)ctx->sort.key[0], n, c.lbt);
     hipLaunchKernelGGL(k_build_init, dim3(1), dim3(64), 0, st, c, n);
     uint32_t cap = (uint32_t)ctx->cap_cells;
-    for (int l = 0; l < kLevels - 1; ++l) {
+    const int L = grid_levels < 0 ? 0 : (grid_levels > kLevels - 1 ? kLevels - 1 : grid_levels);
+    for (int l = 0; l < L; ++l) {
         hipLaunchKernelGGL(k_build_count, dim3(kBuildGrid), dim3(kBuildThreads), 0, st, c,
                            (const uint64_t *)ctx->sort.key[0], l, (uint32_t)ctx->p.nleaf);
         hipLaunchKernelGGL(k_build_scan, dim3(1), dim3(kBuildThreads), 0, st, c, l, cap,
@@ -233,6 +330,9 @@ void launch_build(bh_ctx *ctx, uint32_t n, hipStream_t st) {
         hipLaunchKernelGGL(k_build_write, dim3(kBuildGrid), dim3(kBuildThreads), 0, st, c,
                            (const uint64_t *)ctx->sort.key[0], l, cap);
     }
+    hipLaunchKernelGGL(k_build_tail, dim3(1), dim3(kTailThreads), 0, st, c,
+                       (const uint64_t *)ctx->sort.key[0], L, (uint32_t)ctx->p.nleaf, cap,
+                       ctx->status, (volatile uint32_t *)ctx->hint_dev, ctx->build_gen);
 }
 
 // ---- groups -----------------------------------------------------------------

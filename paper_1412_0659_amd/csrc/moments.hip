@@ -98,51 +98,63 @@ __global__ __launch_bounds__(256) void k_moments_leaf(Cells c, const float *__re
 
 // A parent reads the mass and first moments of its (at most eight) children
 // at once, then sums them in child order.
+__device__ __forceinline__ void up_cell(const Cells &c, uint32_t i) {
+    const uint32_t nch = c.nchild[i];
+    if (nch == 0) return;
+    const uint32_t k0 = c.child0[i];
+    double cm[8], cs0[8], cs1[8], cs2[8];
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) {
+        const uint32_t j = k0 + (k < nch ? k : 0u);
+        cm[k] = c.M[j]; cs0[k] = c.S[3 * j]; cs1[k] = c.S[3 * j + 1]; cs2[k] = c.S[3 * j + 2];
+    }
+    double mm = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) {
+        if (k < nch) {
+            mm = mm + cm[k];
+            s0 = s0 + cs0[k];
+            s1 = s1 + cs1[k];
+            s2 = s2 + cs2[k];
+        }
+    }
+    double c0 = s0 / mm, c1 = s1 / mm, c2 = s2 / mm;
+    double q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < 8; ++k) {
+        if (k < nch) {
+            const uint32_t j = k0 + k;
+            const double mk = cm[k];
+            double d0 = c.com[3 * j] - c0, d1 = c.com[3 * j + 1] - c1, d2 = c.com[3 * j + 2] - c2;
+            const double *qk = c.Q + 6 * (size_t)j;
+            q0 = q0 + (qk[0] + (mk * d0) * d0);
+            q1 = q1 + (qk[1] + (mk * d1) * d1);
+            q2 = q2 + (qk[2] + (mk * d2) * d2);
+            q3 = q3 + (qk[3] + (mk * d0) * d1);
+            q4 = q4 + (qk[4] + (mk * d0) * d2);
+            q5 = q5 + (qk[5] + (mk * d1) * d2);
+        }
+    }
+    c.M[i] = mm;
+    c.S[3 * i] = s0; c.S[3 * i + 1] = s1; c.S[3 * i + 2] = s2;
+    c.com[3 * i] = c0; c.com[3 * i + 1] = c1; c.com[3 * i + 2] = c2;
+    double *q = c.Q + 6 * (size_t)i;
+    q[0] = q0; q[1] = q1; q[2] = q2; q[3] = q3; q[4] = q4; q[5] = q5;
+}
+
 __global__ __launch_bounds__(256) void k_moments_up(Cells c, int l) {
     uint32_t first = c.ls[l], last = c.ls[l + 1];
-    for (uint32_t i = first + blockIdx.x * 256 + threadIdx.x; i < last;
-         i += gridDim.x * 256) {
-        const uint32_t nch = c.nchild[i];
-        if (nch == 0) continue;
-        const uint32_t k0 = c.child0[i];
-        double cm[8], cs0[8], cs1[8], cs2[8];
-#pragma unroll
-        for (uint32_t k = 0; k < 8; ++k) {
-            const uint32_t j = k0 + (k < nch ? k : 0u);
-            cm[k] = c.M[j]; cs0[k] = c.S[3 * j]; cs1[k] = c.S[3 * j + 1]; cs2[k] = c.S[3 * j + 2];
-        }
-        double mm = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-#pragma unroll
-        for (uint32_t k = 0; k < 8; ++k) {
-            if (k < nch) {
-                mm = mm + cm[k];
-                s0 = s0 + cs0[k];
-                s1 = s1 + cs1[k];
-                s2 = s2 + cs2[k];
-            }
-        }
-        double c0 = s0 / mm, c1 = s1 / mm, c2 = s2 / mm;
-        double q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0;
-#pragma unroll
-        for (uint32_t k = 0; k < 8; ++k) {
-            if (k < nch) {
-                const uint32_t j = k0 + k;
-                const double mk = cm[k];
-                double d0 = c.com[3 * j] - c0, d1 = c.com[3 * j + 1] - c1, d2 = c.com[3 * j + 2] - c2;
-                const double *qk = c.Q + 6 * (size_t)j;
-                q0 = q0 + (qk[0] + (mk * d0) * d0);
-                q1 = q1 + (qk[1] + (mk * d1) * d1);
-                q2 = q2 + (qk[2] + (mk * d2) * d2);
-                q3 = q3 + (qk[3] + (mk * d0) * d1);
-                q4 = q4 + (qk[4] + (mk * d0) * d2);
-                q5 = q5 + (qk[5] + (mk * d1) * d2);
-            }
-        }
-        c.M[i] = mm;
-        c.S[3 * i] = s0; c.S[3 * i + 1] = s1; c.S[3 * i + 2] = s2;
-        c.com[3 * i] = c0; c.com[3 * i + 1] = c1; c.com[3 * i + 2] = c2;
-        double *q = c.Q + 6 * (size_t)i;
-        q[0] = q0; q[1] = q1; q[2] = q2; q[3] = q3; q[4] = q4; q[5] = q5;
+    for (uint32_t i = first + blockIdx.x * 256 + threadIdx.x; i < last; i += gridDim.x * 256)
+        up_cell(c, i);
+}
+
+// Levels 20 down to l1 in one workgroup (the deep end of the tree, few or no
+// internal cells), the same per-cell sums as k_moments_up.
+__global__ __launch_bounds__(1024) void k_moments_tail(Cells c, int l1) {
+    for (int l = kLevels - 2; l >= l1; --l) {
+        const uint32_t first = c.ls[l], last = c.ls[l + 1];
+        for (uint32_t i = first + threadIdx.x; i < last; i += 1024) up_cell(c, i);
+        __syncthreads();  // the next level up reads these cells
     }
 }
 
@@ -187,13 +199,17 @@ __global__ __launch_bounds__(256) void k_moments_final(Cells c, const float *__r
     }
 }
 
-void launch_moments(bh_ctx *ctx, hipStream_t st) {
+// Internal cells of levels grid_levels .. 20 by k_moments_tail, the levels
+// above by one grid launch each.
+void launch_moments(bh_ctx *ctx, hipStream_t st, int grid_levels) {
     const State &s = ctx->st[ctx->cur];
     Cells &c = ctx->cells;
     hipLaunchKernelGGL(k_moments_leaf, dim3(kGrid * 2), dim3(256), 0, st, c,
                        (const float *)s.x, (const float *)s.y, (const float *)s.z,
                        (const float *)s.m);
-    for (int l = kLevels - 2; l >= 0; --l)
+    const int L = grid_levels < 0 ? 0 : (grid_levels > kLevels - 1 ? kLevels - 1 : grid_levels);
+    if (L < kLevels - 1) hipLaunchKernelGGL(k_moments_tail, dim3(1), dim3(1024), 0, st, c, L);
+    for (int l = L - 1; l >= 0; --l)
         hipLaunchKernelGGL(k_moments_up, dim3(kGrid), dim3(256), 0, st, c, l);
     hipLaunchKernelGGL(k_moments_final, dim3(kGrid * 2), dim3(256), 0, st, c,
                        (const float *)ctx->box, (int)ctx->p.curve);

@@ -50,6 +50,36 @@ def test_tree_bit_exact(oracle, name, pos, mass):
     t.close()
 
 
+@pytest.mark.parametrize("grid_levels", [0, 3, 9])
+def test_tree_from_the_tail_kernel(oracle, monkeypatch, grid_levels):
+    """The deep levels of every build are split by one workgroup.  With the
+    grid kernels held to the top `grid_levels` levels (0: the whole tree in
+    that workgroup) the tree and its moments are the oracle's, bit for bit;
+    after leapfrog steps, identical to those of a context that builds the
+    usual way (whose rebuilds take the depth of a recent tree)."""
+    name, pos, mass = CASES[-1]
+    print(f"tail case {name} n={len(mass)} grid levels {grid_levels}", flush=True)
+    rng = np.random.default_rng(5)
+    vel = (rng.normal(size=pos.shape) * 0.1).astype(np.float32)
+    monkeypatch.setenv("BH_BUILD_GRID_LEVELS", str(grid_levels))
+    t = gpu_tree(pos, mass, vel=vel)
+    monkeypatch.delenv("BH_BUILD_GRID_LEVELS")
+    ref = gpu_tree(pos, mass, vel=vel)
+    ot = oracle.build_tree(pos, mass)
+    assert_tree_equal(t, ot)
+    for arr in ("mom_M", "mom_com", "mom_Q"):
+        assert np.array_equal(t.export(arr), ot.mom[arr[4:]])
+    names = ("keys", "perm", "level_start", "cell_prefix", "cell_begin", "cell_count",
+             "cell_child0", "cell_nchild", "cell_parent", "mom_M", "mom_com", "mom_Q")
+    for step in range(4):
+        t.step(1e-3, 0.5, 0.01)
+        ref.step(1e-3, 0.5, 0.01)
+        for arr in names:
+            assert np.array_equal(t.export(arr), ref.export(arr)), (step, arr)
+    t.close()
+    ref.close()
+
+
 @pytest.mark.parametrize("name,pos,mass", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("theta,eps", [(0.5, 0.01), (0.4, 0.005), (0.75, 0.0)])
 def test_walk_parity(oracle, name, pos, mass, theta, eps):
