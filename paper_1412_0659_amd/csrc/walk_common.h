@@ -193,10 +193,12 @@ __device__ __forceinline__ void traverse(const TreeView &tv, const GroupBox &b, 
             cnt_pp += nl;
         }
         // ---- particles of opened leaves -> particle-particle index list
-        const uint32_t lc = (!kLeafCells && openleaf) ? (N.y & ~kLeafBit) : 0u;
-        const uint32_t lincl = wave_incl_scan(lc, lane);
-        const uint32_t P = read_lane(lincl, 63u);
-        if (P > 0u) {
+        // (a leaf holds at least one particle: no opened leaf, nothing to scan)
+        const bool pleaf = !kLeafCells && openleaf;
+        if (ballot(pleaf) != 0ull) {
+            const uint32_t lc = pleaf ? (N.y & ~kLeafBit) : 0u;
+            const uint32_t lincl = wave_incl_scan(lc, lane);
+            const uint32_t P = read_lane(lincl, 63u);
             L.offs[lane] = lincl - lc;
             L.firsts[lane] = N.x;
             __syncthreads();
