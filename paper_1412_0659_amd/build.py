@@ -18,7 +18,6 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbh.so")
-PROBE = os.path.join(PKG, "valu_rates")
 ARCH = "gfx950"
 
 CFLAGS = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=off",
@@ -58,13 +57,6 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
-    # the instruction-rate microbenchmark (a measurement, not part of the library)
-    probe = os.path.join(CSRC, "probe", "valu_rates.hip")
-    cmd = [hipcc(), "-std=c++17", "-O3", f"--offload-arch={ARCH}", "-Xclang", "-target-feature",
-           "-Xclang", "-packed-fp32-ops", "-o", PROBE, probe]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"probe build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     if verbose:
         print(LIB, file=sys.stderr)
     return LIB
