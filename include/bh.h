@@ -153,9 +153,48 @@ int leapfrog_step(bh_ctx *ctx, float dt, float theta, float eps, hipStream_t s);
 int tree_force_vjp(bh_ctx *ctx, float theta, float eps, const float *u, float coef,
                    float *g_pos, float *g_mass, hipStream_t s);
 
-/* Transpose of the leapfrog drift x += dt v for the adjoint sweep:
- * gv += dt * gx (device, [n][3], caller order). */
+/* Transpose of the drift x += dt v of the kick-drift-kick leapfrog
+ * (Sec. III.B.2) for the adjoint sweep: gv += dt * gx (device, [n][3],
+ * caller order).  Errors: BH_EINVAL (null pointer, dt not finite),
+ * BH_ESTATE (no state). */
 int leapfrog_vjp_drift(bh_ctx *ctx, float dt, const float *gx, float *gv, hipStream_t s);
+
+/* Flags of leapfrog_vjp_segment. */
+enum {
+    BH_SEG_FIRST = 1, /* the segment starts at the trajectory's initial state:
+                         its first kick transpose takes dt/2 */
+    BH_SEG_LAST = 2   /* the segment ends at the trajectory's final state: the
+                         last step's closing half kick is transposed first */
+};
+
+/* Reverse sweep of k kick-drift-kick leapfrog steps (Sec. III.B.2) from a
+ * checkpoint, with the walk's decisions held fixed as in tree_force_vjp.
+ *   snap      device, a snapshot of the state x_s at the segment's first step
+ *             (bh_save_state of this context with n particles); read only
+ *   k         steps in the segment, >= 1
+ *   flags     BH_SEG_FIRST / BH_SEG_LAST (0 for an interior segment)
+ *   dt, theta, eps   those of the forward steps (leapfrog_step)
+ *   gx, gv    device, [n][3] caller order: cotangents of (x, v) after the
+ *             segment's k steps; read only
+ *   gx0, gv0  device, [n][3]: overwritten with the cotangents of (x, v) at
+ *             the segment's start; they may be the same buffers as gx, gv
+ *   gm        device, [n]: the masses' gradient is ADDED to it (may be NULL)
+ * The call restores snap, recomputes the states inside the segment with
+ * leapfrog_step (so trees and decisions are bit-identical to the forward
+ * run's), then walks back step by step: the drift transpose gv += dt gx and
+ * one force adjoint per position, gx += c J^T gv, gm += c Jm^T gv, where the
+ * two half kicks meeting at an interior position share c = dt, and c = dt/2
+ * at the trajectory's ends (BH_SEG_FIRST, BH_SEG_LAST).  Calling it once per
+ * checkpoint segment, last segment first, gives the K-step gradient.
+ * On return the context holds a state of the segment (not the caller's
+ * latest).  The k - 1 recomputed states are kept in a context-owned device
+ * buffer of (k - 1) * bh_state_bytes() bytes, allocated on first need and
+ * grown when a call needs more.  Errors: BH_EINVAL (null pointer, k < 1,
+ * unknown flags, dt / theta / eps out of range, context without
+ * adjoint = 1), BH_ECAPACITY (n > n_max), BH_ENOMEM (segment buffer). */
+int leapfrog_vjp_segment(bh_ctx *ctx, const void *snap, int64_t n, int32_t k, int32_t flags,
+                         float dt, float theta, float eps, const float *gx, const float *gv,
+                         float *gx0, float *gv0, float *gm, hipStream_t s);
 
 /* Bytes of a state snapshot for the current n (0 if nothing built). */
 int64_t bh_state_bytes(const bh_ctx *ctx);

@@ -4,8 +4,9 @@
 full rebuild per step) and differentiates the final state with respect to
 the initial positions, velocities and masses, holding the walk's decisions
 fixed.  Every arithmetic step runs in the HIP library: the forward steps
-(leapfrog_step), the adjoint of the force (tree_force_vjp) and of the drift
-(leapfrog_vjp_drift).  Memory is bounded by checkpointing: an exact state
+(leapfrog_step) and, per checkpoint segment, the reverse sweep
+(leapfrog_vjp_segment: the segment's recomputation, the adjoints of the force
+and of the drift).  Memory is bounded by checkpointing: an exact state
 snapshot is kept every ``every`` steps and each segment is recomputed during
 the backward sweep, reproducing bit-identical trees.
 
@@ -36,9 +37,8 @@ class LeapfrogFn(torch.autograd.Function):
             tree.step(dt, theta, eps)
             if (k + 1) % every == 0 and k + 1 < steps:
                 ckpts[k + 1] = tree.save()
-        final = tree.save()
         xK, vK = tree.state()
-        ctx.tree, ctx.ckpts, ctx.final = tree, ckpts, final
+        ctx.tree, ctx.ckpts = tree, ckpts
         ctx.params = (float(dt), int(steps), float(theta), float(eps))
         return xK, vK
 
@@ -51,22 +51,13 @@ class LeapfrogFn(torch.autograd.Function):
         gx = (gxK if gxK is not None else torch.zeros(n, 3, device=dev)).float().contiguous().clone()
         gv = (gvK if gvK is not None else torch.zeros(n, 3, device=dev)).float().contiguous().clone()
         gm = torch.zeros(n, device=dev, dtype=torch.float32)
-        h = 0.5 * dt
-        tree.restore(ctx.final)
-        tree.force_vjp(theta, eps, gv, h, gx, gm)
         starts = sorted(ctx.ckpts)
-        for si in reversed(range(len(starts))):
+        for si in reversed(range(len(starts)) if steps > 0 else ()):
             s0 = starts[si]
             s1 = starts[si + 1] if si + 1 < len(starts) else steps
-            tree.restore(ctx.ckpts[s0])
-            snaps = [ctx.ckpts[s0]]
-            for _ in range(s0, s1 - 1):
-                tree.step(dt, theta, eps)
-                snaps.append(tree.save())
-            for j in reversed(range(s0, s1)):
-                B.leapfrog_vjp_drift(tree.ctx, dt, gx, gv)
-                tree.restore(snaps[j - s0])
-                tree.force_vjp(theta, eps, gv, dt if j > 0 else h, gx, gm)
+            flags = (B.BH_SEG_FIRST if s0 == 0 else 0) | (B.BH_SEG_LAST if s1 == steps else 0)
+            B.leapfrog_vjp_segment(tree.ctx, ctx.ckpts[s0], n, s1 - s0, flags, dt, theta, eps,
+                                   gx, gv, gm=gm)
         return gx, gv, gm, None, None, None, None, None, None
 
 

@@ -69,7 +69,7 @@ SYMBOLS = ["bh_create", "bh_destroy", "tree_build", "bh_set_state", "tree_force"
            "bh_state_bytes", "bh_save_state", "bh_load_state", "bh_cic_density",
            "bh_cic_density_vjp", "tree_direct", "bh_diagnostics", "bh_set_box",
            "bh_decompose", "bh_decompose_sampled", "bh_domain_extract", "tree_force_add", "bh_boundary",
-           "bh_let_build", "tree_force_let"]
+           "bh_let_build", "tree_force_let", "leapfrog_vjp_segment"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -104,6 +104,8 @@ def load():
         "bh_last_error": ([_vp], ctypes.c_char_p),
         "tree_force_vjp": ([_vp, f32, f32, _vp, f32, _vp, _vp, _vp], c_int),
         "leapfrog_vjp_drift": ([_vp, f32, _vp, _vp, _vp], c_int),
+        "leapfrog_vjp_segment": ([_vp, _vp, i64, ctypes.c_int32, ctypes.c_int32, f32, f32, f32,
+                                  _vp, _vp, _vp, _vp, _vp, _vp], c_int),
         "bh_state_bytes": ([_vp], i64),
         "bh_save_state": ([_vp, _vp, _vp], c_int),
         "bh_load_state": ([_vp, _vp, i64, _vp], c_int),
@@ -273,6 +275,24 @@ def tree_force_vjp(ctx, theta, eps, u, coef, g_pos=None, g_mass=None, stream=Non
 
 def leapfrog_vjp_drift(ctx, dt, gx, gv, stream=None):
     _check(ctx, load().leapfrog_vjp_drift(ctx, float(dt), _ptr(gx), _ptr(gv), _stream(stream)))
+
+
+BH_SEG_FIRST, BH_SEG_LAST = 1, 2
+
+
+def leapfrog_vjp_segment(ctx, snap, n, k, flags, dt, theta, eps, gx, gv, gx0=None, gv0=None,
+                         gm=None, stream=None):
+    """Reverse sweep of k leapfrog steps from the snapshot `snap` (uint8
+    device tensor); gx0 / gv0 default to gx / gv (in place), gm accumulates."""
+    import torch
+    if not (isinstance(snap, torch.Tensor) and snap.is_cuda and snap.is_contiguous()):
+        raise TypeError("expected a contiguous CUDA snapshot tensor")
+    gx0 = gx if gx0 is None else gx0
+    gv0 = gv if gv0 is None else gv0
+    _check(ctx, load().leapfrog_vjp_segment(ctx, ctypes.c_void_p(snap.data_ptr()), int(n), int(k),
+                                            int(flags), float(dt), float(theta), float(eps),
+                                            _ptr(gx), _ptr(gv), _ptr(gx0), _ptr(gv0), _ptr(gm),
+                                            _stream(stream)))
 
 
 def bh_state_bytes(ctx) -> int:

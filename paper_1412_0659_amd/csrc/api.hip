@@ -64,7 +64,7 @@ void free_all(bh_ctx *c) {
     Let &t = c->let;
     f(t.wA); f(t.P0); f(t.P1); f(t.P2); f(t.xyzm); f(t.wN); f(t.origin);
     f(t.cmark); f(t.omark); f(t.cscan); f(t.pmark); f(t.pscan); f(t.spart); f(t.word);
-    f(c->cut.S); f(c->cut.cuts);
+    f(c->cut.S); f(c->cut.cuts); f(c->seg);
     if (c->hint_host) (void)hipHostFree(c->hint_host);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -111,19 +111,18 @@ void rebuild(bh_ctx *c, uint32_t n, hipStream_t s, bool fresh) {
     if (fresh) c->hint_gen_min = c->build_gen + 1;
     const int L = grid_levels(c, fresh);
     ++c->build_gen;
-    (void)hipEventRecord(c->ev[0], s);
+    record_event(c, 0, s);
     launch_bbox(c, c->st[c->cur], n, s);
     launch_keys(c, c->st[c->cur], n, s);
     launch_radix_sort(c, n, s);
     launch_gather(c, n, s);
-    (void)hipEventRecord(c->ev[1], s);
+    record_event(c, 1, s);
     launch_build(c, n, s, L);
     launch_groups(c, n, s);
     launch_count_leaves(c, s);
-    (void)hipEventRecord(c->ev[2], s);
+    record_event(c, 2, s);
     launch_moments(c, s, L);
-    (void)hipEventRecord(c->ev[3], s);
-    c->ev_rec[0] = c->ev_rec[1] = c->ev_rec[2] = c->ev_rec[3] = true;
+    record_event(c, 3, s);
     c->built = true;
     c->have_acc = false;
     c->counts_valid = false;
@@ -407,14 +406,13 @@ int leapfrog_step(bh_ctx *c, float dt, float theta, float eps, hipStream_t s) {
     if (!valid_eps(eps)) return fail(c, BH_EINVAL, "eps must be finite and >= 0");
     if (!c->built) return fail(c, BH_ESTATE, "leapfrog_step before tree_build");
     uint32_t n = (uint32_t)c->n;
-    (void)hipEventRecord(c->ev[6], s);
+    record_event(c, 6, s);
     if (!c->have_acc || theta != c->acc_theta || eps != c->acc_eps) force(c, theta, eps, s);
     launch_kick_drift(c, 0.5f * dt, dt, n, s);
     rebuild(c, n, s, false);
     force(c, theta, eps, s);
     launch_kick(c, 0.5f * dt, n, s);
-    (void)hipEventRecord(c->ev[7], s);
-    c->ev_rec[6] = c->ev_rec[7] = true;
+    record_event(c, 7, s);
     BH_HIP(c, hipGetLastError());
     return BH_OK;
 }
@@ -590,6 +588,53 @@ int leapfrog_vjp_drift(bh_ctx *c, float dt, const float *gx, float *gv, hipStrea
     if (!gx || !gv || !std::isfinite(dt)) return fail(c, BH_EINVAL, "bad arguments");
     if (!c->built) return fail(c, BH_ESTATE, "no state");
     launch_axpy3(gx, gv, dt, (uint32_t)c->n, s);
+    BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+int leapfrog_vjp_segment(bh_ctx *c, const void *snap, int64_t n, int32_t k, int32_t flags,
+                         float dt, float theta, float eps, const float *gx, const float *gv,
+                         float *gx0, float *gv0, float *gm, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!snap || !gx || !gv || !gx0 || !gv0) return fail(c, BH_EINVAL, "null pointer");
+    if (k < 1) return fail(c, BH_EINVAL, "k must be >= 1");
+    if (flags & ~(BH_SEG_FIRST | BH_SEG_LAST)) return fail(c, BH_EINVAL, "unknown flags");
+    if (!std::isfinite(dt)) return fail(c, BH_EINVAL, "dt must be finite");
+    if (!valid_theta(theta)) return fail(c, BH_EINVAL, "theta must be in (0, 1]");
+    if (!valid_eps(eps)) return fail(c, BH_EINVAL, "eps must be finite and >= 0");
+    if (!c->p.adjoint) return fail(c, BH_EINVAL, "context created without adjoint = 1");
+    int rc = check_n(c, n);
+    if (rc) return rc;
+    const size_t vec = 3 * sizeof(float) * (size_t)n;
+    const int64_t per = n * (int64_t)(7 * sizeof(float) + sizeof(uint32_t) +
+                                      (c->p.pos_fp64 ? 3 * sizeof(double) : 0));
+    std::string err;
+    if (k > 1 && !grow(&c->seg, c->seg_cap, (int64_t)(k - 1) * per, err))
+        return fail(c, BH_ENOMEM, err);
+    if (gx0 != gx) BH_HIP(c, hipMemcpyAsync(gx0, gx, vec, hipMemcpyDeviceToDevice, s));
+    if (gv0 != gv) BH_HIP(c, hipMemcpyAsync(gv0, gv, vec, hipMemcpyDeviceToDevice, s));
+    const float h = 0.5f * dt;
+    const bool last = (flags & BH_SEG_LAST) != 0;
+    // recompute the segment: state j (j = 1 .. k - 1) into seg[j - 1]
+    if ((rc = bh_load_state(c, snap, n, s))) return rc;
+    for (int32_t j = 1; j < k; ++j) {
+        if ((rc = leapfrog_step(c, dt, theta, eps, s))) return rc;
+        if ((rc = bh_save_state(c, c->seg + (size_t)(j - 1) * (size_t)per, s))) return rc;
+    }
+    if (last) {  // the closing half kick of the final step, at x_k
+        if ((rc = leapfrog_step(c, dt, theta, eps, s))) return rc;
+        if ((rc = tree_force_vjp(c, theta, eps, gv0, h, gx0, gm, s))) return rc;
+    }
+    for (int32_t j = k - 1; j >= 0; --j) {
+        if ((rc = leapfrog_vjp_drift(c, dt, gx0, gv0, s))) return rc;
+        // the context holds state k - 1 after the recompute unless it went on to x_k
+        if (j < k - 1 || last) {
+            const void *src = j == 0 ? snap : (const void *)(c->seg + (size_t)(j - 1) * (size_t)per);
+            if ((rc = bh_load_state(c, src, n, s))) return rc;
+        }
+        const float coef = (j == 0 && (flags & BH_SEG_FIRST)) ? h : dt;
+        if ((rc = tree_force_vjp(c, theta, eps, gv0, coef, gx0, gm, s))) return rc;
+    }
     BH_HIP(c, hipGetLastError());
     return BH_OK;
 }

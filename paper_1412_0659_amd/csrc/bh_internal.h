@@ -152,6 +152,8 @@ struct bh_ctx {
     double *cic = nullptr;       // [65536] accumulator of the surface-density grid
     uint32_t *inv = nullptr;     // [n] sorted slot of each caller index (direct sum)
     double *diag = nullptr;      // [kDiagBlocks + 1][kDiagN] diagnostics partials, result
+    uint8_t *seg = nullptr;      // recomputed states of an adjoint segment (grown on demand)
+    int64_t seg_cap = 0;         // bytes of seg
 
     bh::Boundary bnd{};
     bh::Let let{};
@@ -270,6 +272,14 @@ void launch_fill_u32(uint32_t *p, uint32_t v, uint64_t n, hipStream_t st);
 void launch_cut(bh_ctx *c, int32_t p, int64_t C, uint64_t *S, int64_t *cuts, hipStream_t st);
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+// Record timing event k of the context on st (contexts without events, such
+// as the one tree_force_static assembles over its static buffer, skip it).
+inline void record_event(bh_ctx *c, int k, hipStream_t st) {
+    if (!c->ev[k]) return;
+    (void)hipEventRecord(c->ev[k], st);
+    c->ev_rec[k] = true;
+}
 
 // Peano-Hilbert curve (the curve of Sec. III.B.1), after J. Skilling,
 // "Programming the Hilbert curve", AIP Conf. Proc. 707, 381 (2004): integer

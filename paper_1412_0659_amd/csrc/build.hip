@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kTailThreads) void k_build_tail(Cells c,
         last = next;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && hint) {
         hint[0] = gen;
         __threadfence_system();
         for (int k = 0; k < kLevels + 1; ++k) hint[2 + k] = c.ls[k];

@@ -472,10 +472,7 @@ void launch_walk_view(bh_ctx *c, const SrcView &v, float eps, bool remote, bool 
     a.accum = accum ? 1u : 0u;
     hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(64), 0, st, c->work);
     const bool own = !remote && !accum;  // the timed walk of the context's own tree
-    if (own) {
-        (void)hipEventRecord(c->ev[4], st);
-        c->ev_rec[4] = true;
-    }
+    if (own) record_event(c, 4, st);
     const bool f16 = c->p.far_fp16 != 0;
     if (eps == 0.f && f16)
         hipLaunchKernelGGL((k_walk<true, true>), dim3(c->walk_grid), dim3(64), 0, st, a);
@@ -485,10 +482,7 @@ void launch_walk_view(bh_ctx *c, const SrcView &v, float eps, bool remote, bool 
         hipLaunchKernelGGL((k_walk<false, true>), dim3(c->walk_grid), dim3(64), 0, st, a);
     else
         hipLaunchKernelGGL((k_walk<false, false>), dim3(c->walk_grid), dim3(64), 0, st, a);
-    if (own) {
-        (void)hipEventRecord(c->ev[5], st);
-        c->ev_rec[5] = true;
-    }
+    if (own) record_event(c, 5, st);
 }
 
 SrcView own_view(const bh_ctx *c) {

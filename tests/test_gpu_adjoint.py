@@ -5,9 +5,13 @@
 * the cloud-in-cell surface density and its adjoint against the FP64 oracle;
 * the K-step gradient (64 KDK steps, checkpoints every 8) of a linear
   functional and of the surface-density loss, with respect to the initial
-  positions, velocities and masses, against the oracle's reverse sweep and
-  against central finite differences of the oracle's frozen-decision map;
-* in the theta -> 0 limit, against the gradient of the FP64 direct sum.
+  positions, velocities and masses, each array element by element against
+  the oracle's reverse sweep, and along 16 directions (one perturbing only
+  the masses) against central finite differences of the oracle's
+  frozen-decision map;
+* in the theta -> 0 limit, against the gradient of the FP64 direct sum;
+* per theta, the tree gradient against the FP64 direct-sum gradient;
+* the C ABI's segment sweep against one assembled from per-step calls.
 
 The oracle follows its own FP64 trajectory; the trees along it are those of
 the FP32-rounded positions, as on the GPU, which keeps the FP64 position
@@ -142,30 +146,79 @@ def _oracle_decisions(oracle, s, theta, steps):
     return oracle.trajectory_decisions(poss, s.mass, theta)
 
 
+NAMES = ("g_x0", "g_v0", "g_m")
+
+
 def _directional(g, d):
     return sum((a * b).sum() for a, b in zip(g, d))
 
 
+def _fd_directions(s, rng, ndir):
+    """ndir directions (dx0, dv0, dm): the first perturbs only the masses,
+    the second only the positions, the third only the velocities; the rest
+    all three."""
+    m = s.mass.astype(np.float64)
+    out = []
+    for k in range(ndir):
+        dx = rng.normal(size=(s.n, 3))
+        dv = rng.normal(size=(s.n, 3)) * 0.3
+        dm = rng.normal(size=s.n) * m
+        if k == 0:
+            dx, dv = dx * 0, dv * 0
+        elif k == 1:
+            dv, dm = dv * 0, dm * 0
+        elif k == 2:
+            dx, dm = dx * 0, dm * 0
+        out.append((dx, dv, dm))
+    return out
+
+
 def _check_fd(oracle_loss, s, g_gpu, rng, ndir, tol):
+    """Directional derivatives of the GPU gradient against central finite
+    differences of the oracle's frozen-decision map (FP64)."""
     m = s.mass.astype(np.float64)
     x0, v0 = s.pos.astype(np.float64), s.vel.astype(np.float64)
-    for _ in range(ndir):
-        d = (rng.normal(size=x0.shape), rng.normal(size=v0.shape) * 0.3, rng.normal(size=m.shape) * m)
+    worst = 0.0
+    for k, d in enumerate(_fd_directions(s, rng, ndir)):
         h = 1e-6
         fd = (oracle_loss(x0 + h * d[0], v0 + h * d[1], m + h * d[2])
               - oracle_loss(x0 - h * d[0], v0 - h * d[1], m - h * d[2])) / (2 * h)
         an = _directional(g_gpu, d)
-        print(f"  FD {fd:.9e}  GPU adjoint {an:.9e}  rel {abs(fd - an) / abs(fd):.2e}")
-        assert abs(fd - an) <= tol * abs(fd)
+        rel = abs(fd - an) / abs(fd)
+        worst = max(worst, rel)
+        print(f"  FD dir {k:2d}: {fd:.9e}  GPU adjoint {an:.9e}  rel {rel:.2e}")
+        assert rel <= tol, (k, fd, an)
+    print(f"  FD: {ndir} directions, worst rel {worst:.2e}")
 
 
-def _vec_err(g_gpu, g_ref):
-    num = np.sqrt(sum(((a - b) ** 2).sum() for a, b in zip(g_gpu, g_ref)))
-    return num / np.sqrt(sum((b ** 2).sum() for b in g_ref))
+def _per_array(g_gpu, g_ref, floor_frac=1e-3):
+    """For each of g_x0, g_v0, g_m: relative L2 error of the whole array and
+    the per-particle relative error |g_i - ref_i| / max(|ref_i|, floor), the
+    floor being floor_frac of the array's largest per-particle norm."""
+    out = {}
+    for name, a, b in zip(NAMES, g_gpu, g_ref):
+        a2 = np.asarray(a, np.float64).reshape(len(a), -1)
+        b2 = np.asarray(b, np.float64).reshape(len(b), -1)
+        l2 = np.linalg.norm(a2 - b2) / np.linalg.norm(b2)
+        nb = np.linalg.norm(b2, axis=1)
+        e = np.linalg.norm(a2 - b2, axis=1) / np.maximum(nb, floor_frac * nb.max())
+        out[name] = (l2, float(np.median(e)), float(np.percentile(e, 99)))
+    return out
+
+
+def _gate_per_array(label, g_gpu, g_ref, l2_tol=1e-4, med_tol=1e-4, p99_tol=1e-3):
+    """Each array separately: relative L2 <= 1e-4, per-particle median <=
+    1e-4 and 99th percentile <= 1e-3 (the force bar's 1:10 median:p99
+    ratio)."""
+    errs = _per_array(g_gpu, g_ref)
+    for name, (l2, med, p99) in errs.items():
+        print(f"{label} {name}: rel L2 {l2:.2e}, per-particle median {med:.2e} p99 {p99:.2e}")
+    for name, (l2, med, p99) in errs.items():
+        assert l2 <= l2_tol and med <= med_tol and p99 <= p99_tol, (label, name, l2, med, p99)
+    return errs
 
 
 def test_leapfrog_gradient_of_linear_functional(oracle):
-    import torch
     s = ics.disk_halo_scaled(W["n"], W["seed"])
     theta, K, every = W["theta"], W["steps"], W["every"]
     rng = np.random.default_rng(56)
@@ -176,15 +229,13 @@ def test_leapfrog_gradient_of_linear_functional(oracle):
     decs = _oracle_decisions(oracle, s, theta, K)
     m = s.mass.astype(np.float64)
     g_ref = oracle.leapfrog_frozen_vjp(s.pos, s.vel, m, W["dt"], decs, W["eps"], wx, wv)
-    err = _vec_err(g_gpu, g_ref)
-    print(f"linear functional: gradient vector rel err {err:.2e}")
-    assert err <= 1e-4
+    _gate_per_array("linear functional", g_gpu, g_ref)
 
     def L(x0, v0, mm):
         xK, vK, _ = oracle.leapfrog_frozen(x0, v0, mm, W["dt"], decs, W["eps"])
         return (wx * xK).sum() + (wv * vK).sum()
 
-    _check_fd(L, s, g_gpu, rng, 3, 1e-4)
+    _check_fd(L, s, g_gpu, rng, 16, 1e-4)
 
 
 def _loss_parts(oracle, s, theta):
@@ -213,7 +264,7 @@ def _loss_parts(oracle, s, theta):
     return target, loss, grad
 
 
-def _gpu_loss_grad(s, target, theta):
+def _gpu_loss_grad(s, target, theta, every=None):
     import torch
     from paper_1412_0659_amd.autograd import surface_density
     sel = torch.from_numpy(s.is_disk.astype(np.uint8)).to(device())
@@ -223,7 +274,7 @@ def _gpu_loss_grad(s, target, theta):
         sig = surface_density(xK, m, sel, t, W["grid"])
         return ((sig - tgt) ** 2).sum()
 
-    return _gpu_grad(s, fn, theta, W["steps"], W["every"])
+    return _gpu_grad(s, fn, theta, W["steps"], W["every"] if every is None else every)
 
 
 def test_surface_density_loss_gradient(oracle):
@@ -231,20 +282,112 @@ def test_surface_density_loss_gradient(oracle):
     target, loss, grad = _loss_parts(oracle, s, W["theta"])
     g_gpu = _gpu_loss_grad(s, target, W["theta"])
     g_ref = grad()
-    err = _vec_err(g_gpu, g_ref)
-    print(f"surface-density loss: gradient vector rel err {err:.2e}")
-    assert err <= 1e-3
-    _check_fd(loss, s, g_gpu, np.random.default_rng(57), 3, 1e-4)
+    _gate_per_array("surface-density loss", g_gpu, g_ref)
+    _check_fd(loss, s, g_gpu, np.random.default_rng(57), 16, 1e-4)
 
 
 def test_surface_density_loss_gradient_direct_limit(oracle):
     """theta -> 0: every decision a p-p pair; the GPU gradient is that of the
-    FP64 direct-sum leapfrog."""
+    FP64 direct-sum leapfrog, gated at 1e-4 per array."""
     s = ics.disk_halo_scaled(W["n"], W["seed"])
     target, loss, grad = _loss_parts(oracle, s, 1e-6)
     g_gpu = _gpu_loss_grad(s, target, 1e-6)
     g_ref = grad()
-    err = _vec_err(g_gpu, g_ref)
-    print(f"surface-density loss, direct limit: gradient vector rel err {err:.2e}")
-    assert err <= 1e-3
-    _check_fd(loss, s, g_gpu, np.random.default_rng(58), 1, 1e-4)
+    _gate_per_array("surface-density loss, direct limit", g_gpu, g_ref)
+    _check_fd(loss, s, g_gpu, np.random.default_rng(58), 16, 1e-4)
+
+
+def test_tree_gradient_against_direct_sum_per_theta(oracle):
+    """The tree-code's gradient at theta in {0.3, 0.4, 0.6} against the FP64
+    direct-sum gradient of the same loss (the oracle's reverse sweep of the
+    direct-sum leapfrog): cosine and relative L2 per array, reported.  The
+    opening-angle error makes these differ by far more than rounding, so the
+    gate is only that they point the same way and that the error does not
+    shrink as theta grows."""
+    s = ics.disk_halo_scaled(W["n"], W["seed"])
+    target, _, grad = _loss_parts(oracle, s, 1e-6)
+    g_dir = grad()
+    prev = None
+    for theta in (0.3, 0.4, 0.6):
+        g = _gpu_loss_grad(s, target, theta)
+        l2 = []
+        for name, a, b in zip(NAMES, g, g_dir):
+            a, b = a.reshape(-1), b.reshape(-1)
+            cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+            rl2 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+            l2.append(rl2)
+            print(f"theta {theta}: {name} vs FP64 direct-sum gradient: cosine {cos:.6f}, "
+                  f"rel L2 {rl2:.2e}")
+            assert cos > 0.9, (theta, name, cos)
+        if prev is not None:
+            assert max(l2) >= 0.5 * max(prev), (theta, l2, prev)
+        prev = l2
+
+
+def test_vjp_segment_matches_per_step_sweep():
+    """leapfrog_vjp_segment drives the 64-step gradient through the C ABI
+    alone (checkpoints every 8); it matches a sweep assembled from the
+    per-step entry points (bh_load_state, tree_force_vjp,
+    leapfrog_vjp_drift) over a snapshot of every step, and the autograd
+    path, to the FP64 atomics' rounding."""
+    import torch
+    from paper_1412_0659_amd import binding as B
+    from paper_1412_0659_amd.autograd import leapfrog
+    s = ics.disk_halo_scaled(W["n"], W["seed"])
+    n, K, every, dt, theta, eps = s.n, W["steps"], W["every"], W["dt"], W["theta"], W["eps"]
+    rng = np.random.default_rng(59)
+    wx, wv = rng.normal(size=(n, 3)).astype(np.float32), rng.normal(size=(n, 3)).astype(np.float32)
+    t = _dev_tree(n, pos_fp64=True)
+    ctx = t.ctx
+    B.bh_set_state(ctx, to_dev(s.pos), to_dev(s.vel), to_dev(s.mass))
+    nb = B.bh_state_bytes(ctx)
+
+    def snap():
+        buf = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        B.bh_save_state(ctx, buf)
+        return buf
+
+    snaps = [snap()]
+    for _ in range(K):
+        B.leapfrog_step(ctx, dt, theta, eps)
+        snaps.append(snap())
+    # (a) segments of 8 through the C ABI
+    gx, gv, gm = to_dev(wx).clone(), to_dev(wv).clone(), _zeros(n)
+    for s0 in reversed(range(0, K, every)):
+        s1 = min(s0 + every, K)
+        flags = (B.BH_SEG_FIRST if s0 == 0 else 0) | (B.BH_SEG_LAST if s1 == K else 0)
+        B.leapfrog_vjp_segment(ctx, snaps[s0], n, s1 - s0, flags, dt, theta, eps, gx, gv, gm=gm)
+    # separate output buffers leave the inputs untouched
+    gx1, gv1, gx2, gv2 = to_dev(wx).clone(), to_dev(wv).clone(), _zeros(n, 3), _zeros(n, 3)
+    B.leapfrog_vjp_segment(ctx, snaps[K - 1], n, 1, B.BH_SEG_LAST, dt, theta, eps, gx1, gv1, gx2,
+                           gv2, None)
+    t.sync()
+    assert np.array_equal(gx1.cpu().numpy(), wx) and np.array_equal(gv1.cpu().numpy(), wv)
+    # (b) the same sweep from the per-step entry points
+    rx, rv, rm = to_dev(wx).clone(), to_dev(wv).clone(), _zeros(n)
+    B.bh_load_state(ctx, snaps[K], n)
+    B.tree_force_vjp(ctx, theta, eps, rv, 0.5 * dt, rx, rm)
+    for j in reversed(range(K)):
+        B.leapfrog_vjp_drift(ctx, dt, rx, rv)
+        B.bh_load_state(ctx, snaps[j], n)
+        B.tree_force_vjp(ctx, theta, eps, rv, dt if j > 0 else 0.5 * dt, rx, rm)
+    t.sync()
+    seg = [a.cpu().numpy().astype(np.float64) for a in (gx, gv, gm)]
+    ref = [a.cpu().numpy().astype(np.float64) for a in (rx, rv, rm)]
+    for name, a, b in zip(NAMES, seg, ref):
+        e = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print(f"segment vs per-step sweep {name}: rel L2 {e:.2e}")
+        assert e <= 1e-6, (name, e)
+    t.close()
+    # (c) the autograd path (which calls leapfrog_vjp_segment per checkpoint)
+    wx_d, wv_d = to_dev(wx), to_dev(wv)
+    g_auto = _gpu_grad(s, lambda xK, vK, m, tt: (xK * wx_d).sum() + (vK * wv_d).sum(), theta, K,
+                       every)
+    for name, a, b in zip(NAMES, g_auto, ref):
+        e = np.linalg.norm(a - b) / np.linalg.norm(b)
+        print(f"autograd vs per-step sweep {name}: rel L2 {e:.2e}")
+        assert e <= 1e-6, (name, e)
+    # argument checks
+    with pytest.raises(B.BhError):
+        B.leapfrog_vjp_segment(_dev_tree(n, pos_fp64=True).ctx, snaps[0], n, 0, 0, dt, theta,
+                               eps, gx, gv)
