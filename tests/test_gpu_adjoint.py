@@ -297,31 +297,55 @@ def test_surface_density_loss_gradient_direct_limit(oracle):
     _check_fd(loss, s, g_gpu, np.random.default_rng(58), 16, 1e-4)
 
 
+def _cos_l2(a, b):
+    a, b = np.asarray(a).reshape(-1), np.asarray(b).reshape(-1)
+    return (float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b))),
+            float(np.linalg.norm(a - b) / np.linalg.norm(b)))
+
+
 def test_tree_gradient_against_direct_sum_per_theta(oracle):
-    """The tree-code's gradient at theta in {0.3, 0.4, 0.6} against the FP64
-    direct-sum gradient of the same loss (the oracle's reverse sweep of the
-    direct-sum leapfrog): cosine and relative L2 per array, reported.  The
-    opening-angle error makes these differ by far more than rounding, so the
-    gate is only that they point the same way and that the error does not
-    shrink as theta grows."""
+    """Per theta in {0.3, 0.4, 0.6}: the tree-code's 64-step gradient against
+    the FP64 direct-sum gradient (cosine and relative L2 per array), for the
+    surface-density loss and for w . v_K.  The latter's gradient with respect
+    to x_0 and m comes only through the forces, so it shows the opening-angle
+    error, where the density loss's gradient is dominated by the drift.
+    Reported for the GPU and for the oracle's FP64 tree; gated: the GPU
+    gradient within 1e-4 (relative L2 per array) of the oracle's at the same
+    theta, and the oracle tree's distance from the direct-sum gradient growing
+    with theta."""
     s = ics.disk_halo_scaled(W["n"], W["seed"])
-    target, _, grad = _loss_parts(oracle, s, 1e-6)
-    g_dir = grad()
+    m = s.mass.astype(np.float64)
+    dt, K, eps = W["dt"], W["steps"], W["eps"]
+    w = np.random.default_rng(60).normal(size=(s.n, 3))
+    w_d = to_dev(w)
+    zero = np.zeros_like(w)
+
+    def oracle_grad(theta):
+        decs = _oracle_decisions(oracle, s, theta, K)
+        return oracle.leapfrog_frozen_vjp(s.pos, s.vel, m, dt, decs, eps, zero, w)
+
+    g_dir = oracle_grad(1e-6)
+    target, _, sd_grad = _loss_parts(oracle, s, 1e-6)
+    sd_dir = sd_grad()
     prev = None
     for theta in (0.3, 0.4, 0.6):
-        g = _gpu_loss_grad(s, target, theta)
-        l2 = []
-        for name, a, b in zip(NAMES, g, g_dir):
-            a, b = a.reshape(-1), b.reshape(-1)
-            cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
-            rl2 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
-            l2.append(rl2)
-            print(f"theta {theta}: {name} vs FP64 direct-sum gradient: cosine {cos:.6f}, "
-                  f"rel L2 {rl2:.2e}")
-            assert cos > 0.9, (theta, name, cos)
+        g_gpu = _gpu_grad(s, lambda xK, vK, mm, t: (vK * w_d).sum(), theta, K, W["every"])
+        g_orc = oracle_grad(theta)
+        sd_gpu = _gpu_loss_grad(s, target, theta)
+        errs = []
+        for name, a, b, c, d in zip(NAMES, g_gpu, g_orc, g_dir, sd_gpu):
+            cg, lg = _cos_l2(a, c)
+            co, lo = _cos_l2(b, c)
+            _, lgo = _cos_l2(a, b)
+            cs, ls = _cos_l2(d, sd_dir[NAMES.index(name)])
+            print(f"theta {theta} {name}: w.v_K vs direct-sum gradient: GPU cosine {cg:.8f} rel L2 "
+                  f"{lg:.2e}; oracle tree cosine {co:.8f} rel L2 {lo:.2e}; GPU vs oracle tree "
+                  f"{lgo:.2e} | density loss, GPU vs direct: cosine {cs:.8f} rel L2 {ls:.2e}")
+            assert lgo <= 1e-4, (theta, name, lgo)
+            errs.append(lo)
         if prev is not None:
-            assert max(l2) >= 0.5 * max(prev), (theta, l2, prev)
-        prev = l2
+            assert errs[0] > prev[0] and errs[2] > prev[2], (theta, errs, prev)
+        prev = errs
 
 
 def test_vjp_segment_matches_per_step_sweep():
