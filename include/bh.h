@@ -435,6 +435,35 @@ const char *bh_strerror(int status);
 /* Description of the last failure on this context ("" if none). */
 const char *bh_last_error(const bh_ctx *ctx);
 
+/* Largest n of tree_force_static. */
+#define BH_STATIC_MAX_N 65536
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): tree_build
+ * followed by tree_force, with nleaf = 16, ncrit = 64, FP32 terms and Morton
+ * keys, without a context.  Every intermediate buffer (sorted state, keys,
+ * cells, moments, groups, walk stacks) lives in one static device array of
+ * 64 MiB that each device the library runs on holds until the process ends;
+ * the call allocates nothing (no hipMalloc, no host or device allocation by a
+ * library routine).
+ *   pos, mass    device, [n][3] and [n] FP32, caller order (read)
+ *   n            1 .. BH_STATIC_MAX_N
+ *   theta, eps   as tree_force
+ *   acc, pot     device, [n][3] and [n] FP32, caller order (written; either
+ *                may be NULL)
+ *   status       device, one uint32_t (may be NULL): receives the device
+ *                status bits of this call (1 non-finite position, 2 mass <= 0
+ *                or not finite; 0 when clean), valid once s has passed it
+ * Results equal those of tree_build + tree_force on a context with the same
+ * parameters.  Every call on one device shares that device's array and keeps
+ * the last call's contents: calls that overlap on one device (two streams,
+ * two host threads) race and give undefined results; serialise them.
+ * Errors: BH_EINVAL (null pos or mass, n <= 0, theta / eps out of range),
+ * BH_ECAPACITY (n > BH_STATIC_MAX_N), BH_EHIP (a HIP runtime call failed).
+ * There is no context, so bh_last_error has no message for this call. */
+int tree_force_static(const float *pos, const float *mass, int64_t n, float theta, float eps,
+                      float *acc, float *pot, uint32_t *status, hipStream_t s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -69,7 +69,7 @@ SYMBOLS = ["bh_create", "bh_destroy", "tree_build", "bh_set_state", "tree_force"
            "bh_state_bytes", "bh_save_state", "bh_load_state", "bh_cic_density",
            "bh_cic_density_vjp", "tree_direct", "bh_diagnostics", "bh_set_box",
            "bh_decompose", "bh_decompose_sampled", "bh_domain_extract", "tree_force_add", "bh_boundary",
-           "bh_let_build", "tree_force_let", "leapfrog_vjp_segment"]
+           "bh_let_build", "tree_force_let", "leapfrog_vjp_segment", "tree_force_static"]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -125,6 +125,7 @@ def load():
                          ctypes.POINTER(i64), _vp], c_int),
         "bh_let_build": ([_vp, _vp, ctypes.c_int32, f32, _vp, _vp], c_int),
         "tree_force_let": ([_vp, f32, f32, _vp, _vp, _vp, _vp], c_int),
+        "tree_force_static": ([_vp, _vp, i64, f32, f32, _vp, _vp, _vp, _vp], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -397,6 +398,21 @@ def bh_let_build(ctx, srcs, theta, stream=None) -> np.ndarray:
 def tree_force_let(ctx, theta, eps, rows=None, acc=None, pot=None, stream=None):
     _check(ctx, load().tree_force_let(ctx, float(theta), float(eps), _u32ptr(rows), _ptr(acc),
                                       _ptr(pot), _stream(stream)))
+
+
+BH_STATIC_MAX_N = 65536
+
+
+def tree_force_static(pos, mass, theta, eps, acc=None, pot=None, status=None, stream=None):
+    """tree_build + tree_force without a context or any allocation (the
+    library's static device buffer; n <= BH_STATIC_MAX_N).  status: an
+    optional one-element int32 CUDA tensor receiving the device status bits."""
+    n = mass.shape[0]
+    if pos.shape != (n, 3):
+        raise ValueError("pos must be [N, 3]")
+    _check(None, load().tree_force_static(_ptr(pos), _ptr(mass), n, float(theta), float(eps),
+                                          _ptr(acc), _ptr(pot), _u32ptr(status),
+                                          _stream(stream)))
 
 
 class Tree:

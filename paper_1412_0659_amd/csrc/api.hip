@@ -6,8 +6,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "bh_internal.h"
@@ -234,6 +236,101 @@ void weight_cuts(std::vector<std::pair<uint64_t, int64_t>> smp, int32_t pieces,
         }
         S += e.second;
     }
+}
+
+}  // namespace
+
+// ---- the entry point that allocates nothing ----------------------------------
+//
+// tree_force_static runs the whole path (build + walk + unsort) for up to
+// BH_STATIC_MAX_N particles with every intermediate buffer carved out of one
+// file-scope device array, for callers that cannot allocate device memory.
+// Each device the library runs on holds its own copy of the array for the
+// life of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device.
+
+namespace {
+
+constexpr int64_t kStaticMaxN = BH_STATIC_MAX_N;
+constexpr int kStaticWalkGrid = 2048;          // persistent walk waves (stack spill per wave)
+constexpr size_t kStaticBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+
+struct StaticDevice {
+    unsigned char *ptr = nullptr;  // device address of `scratch` on this device
+    int cus = 0, walk_grid = 0;
+};
+StaticDevice g_static[kMaxDevices];
+std::mutex g_static_mu;
+
+// Point every buffer of the path at consecutive 256-byte-aligned pieces of
+// base (nothing is written when base is null); returns the bytes used.
+size_t static_layout(bh_ctx *c, unsigned char *base) {
+    size_t off = 0;
+    auto take = [&](auto **p, size_t count) {
+        using T = std::remove_pointer_t<std::remove_reference_t<decltype(*p)>>;
+        off = (off + 255) & ~size_t(255);
+        *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += sizeof(T) * std::max<size_t>(count, 1);
+    };
+    const size_t n = (size_t)c->nmax, nc = (size_t)c->cap_cells;
+    for (int k = 0; k < 2; ++k) {
+        State &st = c->st[k];
+        take(&st.x, n); take(&st.y, n); take(&st.z, n); take(&st.m, n);
+        take(&st.vx, n); take(&st.vy, n); take(&st.vz, n); take(&st.cid, n);
+        st.x64 = st.y64 = st.z64 = nullptr;
+        take(&c->sort.key[k], n);
+        take(&c->sort.idx[k], n);
+    }
+    c->sort.counts_len = sort_counts_len(c->nmax);
+    c->sort.scan_part_len = std::max(scan_part_len(c->sort.counts_len), scan_part_len(c->nmax));
+    take(&c->sort.counts, (size_t)c->sort.counts_len);
+    take(&c->sort.scan_part, (size_t)c->sort.scan_part_len);
+    take(&c->acc, n); take(&c->xyzm, n);
+    take(&c->spill, (size_t)c->walk_grid * kStackMax);
+    take(&c->box, 8); take(&c->box_part, 6 * 1024); take(&c->status, 4); take(&c->work, 8);
+    take(&c->totals, 4);
+    Cells &q = c->cells;
+    take(&q.prefix, nc); take(&q.level, nc); take(&q.begin, nc); take(&q.count, nc);
+    take(&q.child0, nc); take(&q.nchild, nc); take(&q.parent, nc); take(&q.ls, kLsSize);
+    take(&q.part, kBuildGrid + 1); take(&q.lbt, ((size_t)1 << (3 * kTableLevel)) + 1);
+    take(&q.M, nc); take(&q.S, 3 * nc); take(&q.com, 3 * nc); take(&q.Q, 6 * nc);
+    take(&q.wA, nc); take(&q.wN, nc); take(&q.P0, nc); take(&q.P1, nc); take(&q.P2, nc);
+    take(&q.size, nc);
+    Groups &g = c->groups;
+    take(&g.flag, n); take(&g.scan, n); take(&g.begin, n + 1); take(&g.count_dev, 1);
+    take(&g.box, 2 * n); take(&g.npp, n); take(&g.npc, n);
+    return off;
+}
+
+// Once per device, with that device current: the address of `scratch` there.
+int static_device(int dev, StaticDevice &out) {
+    if (dev < 0 || dev >= kMaxDevices) return BH_EINVAL;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticDevice &d = g_static[dev];
+    if (!d.ptr) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return BH_EHIP;
+        }
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return BH_EHIP;
+        }
+        d.cus = std::max(cus, 1);
+        d.walk_grid = std::min(d.cus * walk_blocks_per_cu(), kStaticWalkGrid);
+        d.ptr = static_cast<unsigned char *>(p);
+    }
+    out = d;
+    return BH_OK;
 }
 
 }  // namespace
@@ -1078,6 +1175,48 @@ int tree_force_let(bh_ctx *c, float theta, float eps, const uint32_t *rows, floa
     if (acc || pot) launch_unsort(c, acc, pot, (uint32_t)c->n, s, rows);
     c->have_acc = false;  // acc holds local + remote forces
     BH_HIP(c, hipGetLastError());
+    return BH_OK;
+}
+
+int tree_force_static(const float *pos, const float *mass, int64_t n, float theta, float eps,
+                      float *acc, float *pot, uint32_t *status, hipStream_t s) {
+    if (!pos || !mass) return BH_EINVAL;
+    if (n <= 0 || !valid_theta(theta) || !valid_eps(eps)) return BH_EINVAL;
+    if (n > kStaticMaxN) return BH_ECAPACITY;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return BH_EHIP;
+    }
+    StaticDevice d;
+    int rc = static_device(dev, d);
+    if (rc) return rc;
+    // a context on the stack whose buffers are pieces of this device's array
+    bh_ctx c;
+    c.nmax = kStaticMaxN;
+    c.cap_cells = kStaticMaxN + 21 * (kStaticMaxN / (16 + 1)) + 1;
+    c.p.nleaf = 16;
+    c.p.ncrit = 64;
+    c.device = dev;
+    c.cus = d.cus;
+    c.walk_grid = d.walk_grid;
+    if (static_layout(&c, d.ptr) > kStaticBytes) return BH_ENOMEM;
+    c.n = n;
+    c.cur = 0;
+    // the array keeps the previous call's contents: clear the status words
+    launch_fill_u32(c.status, 0u, 4, s);
+    launch_ingest(&c, pos, nullptr, mass, (uint32_t)n, s);
+    rebuild(&c, (uint32_t)n, s, true);
+    force(&c, theta, eps, s);
+    if (acc || pot) launch_unsort(&c, acc, pot, (uint32_t)n, s);
+    if (status) {
+        hipError_t e = hipMemcpyAsync(status, c.status, sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return BH_EHIP;
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return BH_EHIP;
     return BH_OK;
 }
 
