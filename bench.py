@@ -28,6 +28,9 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CUs x 2.4 GHz x 256 fl
 WALK_SOURCES = [os.path.join(ROOT, "paper_1412_0659_amd", "csrc", f)
                 for f in ("walk.hip", "walk_common.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "walk_disk_halo_13m_traffic.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "walk_valu_counters_disk_halo_13m.json")
+VJP_SOURCES = [os.path.join(ROOT, "paper_1412_0659_amd", "csrc", f)
+               for f in ("walk_vjp.hip", "walk_common.h")]
 
 
 def paper_flops(n_pp, n_pc):
@@ -35,21 +38,86 @@ def paper_flops(n_pp, n_pc):
     return FLOPS_PP * float(n_pp) + FLOPS_PC * float(n_pc)
 
 
-# Flops our kernel executes per interaction, counted in the gfx950 assembly
-# of the walk's evaluation loops (an FMA as 2, v_rsq_f32 as 4 like the
-# paper): p-p 6 FMA + 7 mul/add/sub + rsq = 23; p-c 22 FMA + 11 mul/sub
-# + rsq = 59 (the paper counts 65 for its p-c term).
-KERNEL_FLOPS_PP = 23
-KERNEL_FLOPS_PC = 59
-
-
-def walk_source_hash():
-    """Hash of the walk kernel's sources (the evaluation and the traversal)."""
+def walk_source_hash(paths=None):
+    """Hash of a kernel's sources (default: the walk's evaluation and traversal)."""
     h = hashlib.sha256()
-    for path in WALK_SOURCES:
+    for path in (WALK_SOURCES if paths is None else paths):
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def load_counters():
+    """Per-dispatch VALU counters of the walk kernels and the force VJP from
+    the committed rocprofv3 summary, each kept only if taken on the current
+    source of its kernel (None otherwise)."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ok_walk = t.get("walk_source_sha256_16") == walk_source_hash()
+    ok_vjp = t.get("vjp_source_sha256_16") == walk_source_hash(VJP_SOURCES)
+    out = {}
+    for name, c in t.get("kernels", {}).items():
+        if (name.startswith("k_walk_vjp") and ok_vjp) or (not name.startswith("k_walk_vjp")
+                                                          and ok_walk):
+            out[name] = c
+    return out or None
+
+
+def counter_flops(c):
+    """FP32 + FP16 VALU flops of one dispatch from its counters: the
+    hardware's own FLOPS counts (transcendentals included; they count per
+    wave instruction, so x 64 lanes), and the count derived from the
+    instruction classes (FMA 2, add / mul / rsq 1 per lane)."""
+    hw = 64.0 * sum(c.get(k, 0.0) for k in (
+        "SQ_INSTS_VALU_FLOPS_FP32", "SQ_INSTS_VALU_FLOPS_FP32_TRANS",
+        "SQ_INSTS_VALU_FLOPS_FP16", "SQ_INSTS_VALU_FLOPS_FP16_TRANS"))
+    ins = 64.0 * (2 * c.get("SQ_INSTS_VALU_FMA_F32", 0.0) + c.get("SQ_INSTS_VALU_MUL_F32", 0.0)
+                  + c.get("SQ_INSTS_VALU_ADD_F32", 0.0) + c.get("SQ_INSTS_VALU_TRANS_F32", 0.0))
+    return hw, ins
+
+
+def pmc_dispatches(paths):
+    """Counter values of every dispatch in rocprofv3 --pmc output databases
+    (sqlite): {kernel: [{counter: value, "ms": duration}, ...]}."""
+    import sqlite3
+    from collections import defaultdict
+    out = defaultdict(list)
+    for db in paths:
+        con = sqlite3.connect(db)
+        q = ("select ks.display_name, kd.id, ip.name, sum(pe.value), kd.end - kd.start "
+             "from rocpd_pmc_event pe join rocpd_info_pmc ip on pe.pmc_id = ip.id "
+             "join rocpd_kernel_dispatch kd on pe.event_id = kd.event_id "
+             "join rocpd_info_kernel_symbol ks on kd.kernel_id = ks.id group by kd.id, ip.name "
+             "order by kd.id")
+        rows = {}
+        for name, did, cname, val, d in con.execute(q):
+            r = rows.setdefault(did, {"kernel": name, "ms": d / 1e6})
+            r[cname] = val
+        con.close()
+        for r in rows.values():
+            out[r.pop("kernel")].append(r)
+    return out
+
+
+def pmc_summary(paths, min_frac=0.0):
+    """Mean counter value per dispatch and mean duration of every kernel in
+    rocprofv3 --pmc output databases; with min_frac only the dispatches at
+    least that fraction of the kernel's longest one (the full-size workload
+    among smaller ones): {kernel: {counter: value}}."""
+    out = {}
+    for name, rows in pmc_dispatches(paths).items():
+        longest = max(r["ms"] for r in rows)
+        sel = [r for r in rows if r["ms"] >= min_frac * longest]
+        keys = sorted({k for r in sel for k in r if k != "ms"})
+        row = {k: sum(r[k] for r in sel if k in r) / max(1, sum(1 for r in sel if k in r))
+               for k in keys}
+        row["dispatches"] = len(sel)
+        row["mean_ms"] = sum(r["ms"] for r in sel) / len(sel)
+        out[name] = row
+    return out
 
 
 def load_traffic():
@@ -63,6 +131,43 @@ def load_traffic():
     if t.get("walk_source_sha256_16") != walk_source_hash():
         return None
     return t.get("hbm_bytes_per_launch")
+
+
+def cpu_model():
+    """Host CPU model name and logical CPU count."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": name, "os_cpu_count": os.cpu_count()}
+
+
+def oracle_anchors(anchors, nanchor=256):
+    """The oracle's FP64 direct sum at the first `nanchor` sampled targets of
+    each GPU error measurement: it checks the GPU's FP64 direct sum (the
+    reference of the full-sample errors) and the walks' errors directly."""
+    import numpy as np
+
+    from oracle import oracle as O
+    out = {}
+    for a in anchors:
+        idx = a["idx"][:nanchor]
+        t0 = time.perf_counter()
+        oa, op = O.direct(a["pos"], a["mass"], np.float32(a["eps"]), targets=idx)
+        dt = time.perf_counter() - t0
+        r = {"targets": int(len(idx)), "oracle_direct_s": dt,
+             "gpu_direct_vs_oracle_max_rel": float(np.max(_rel(a["ref_acc"][:nanchor], oa)))}
+        for k, acc in a["walks"].items():
+            e = _rel(acc[:nanchor], oa)
+            r[k + "_err_acc_median"] = float(np.median(e))
+            r[k + "_err_acc_p99"] = float(np.percentile(e, 99))
+        out[a["name"]] = r
+    return out
 
 
 def cpu_baseline(snap, theta, eps, budget_s=12.0):
@@ -87,14 +192,14 @@ def cpu_baseline(snap, theta, eps, budget_s=12.0):
     targets = int(tree.gcnt[order[:done]].sum())
     return {
         "value": inter / walk_s, "unit": "interactions/s", "cores": O.num_threads(),
-        "kind": "oracle",
+        "kind": "oracle", "cpu": cpu_model(),
         "sample": (f"FP64 oracle walk of {done} random groups ({targets} targets) of the "
                    f"{tree.n}-particle tree, theta={theta}, eps={eps}; {walk_s:.1f} s of walk; "
                    f"oracle tree build over all particles took {t_build:.1f} s (not in value)"),
     }
 
 
-def hbm_phases(n, ncells, ms_sort, ms_moments, pos_fp64=False):
+def hbm_phases(n, ncells, ms_sort, ms_moments, pos_fp64=False, ms_build=None, depth=None):
     """Algorithmic HBM bytes of the tree-build phases and the rate they imply.
 
     Per particle, sort phase: box 12 B read; keys 12 B read + 12 B written
@@ -103,12 +208,20 @@ def hbm_phases(n, ncells, ms_sort, ms_moments, pos_fp64=False):
     16 B (x, y, z, m) record written (+48 B with the FP64 master).
     Moments: 16 B per particle
     read plus, per cell, 16 B of topology read, 104 B of FP64 moments written
-    and read back by the parent pass and 80 B of walk records written."""
+    and read back by the parent pass and 80 B of walk records written.
+    Build (with ms_build and depth): 8 B of keys per particle per splitting
+    level, 36 B written and 4 B read per cell, 12 B per particle for the groups."""
     gather = 4 + 32 + 32 + 16 + (48 if pos_fp64 else 0)
     sort_b = n * (12 + 24 + 8 * 32 + gather)
     mom_b = n * 16 + ncells * (16 + 104 + 104 + 80)
     out = {"sort": {"bytes": sort_b, "ms": ms_sort},
            "moments": {"bytes": mom_b, "ms": ms_moments}}
+    if ms_build is not None and depth is not None:
+        # octree + groups: the keys read once per level that splits cells
+        # (levels 0 .. depth - 1), 36 B written per cell, the group pass
+        # 4 B read per cell and 12 B per particle (flags, scan, begin)
+        out["build"] = {"bytes": n * 8 * int(depth) + ncells * (36 + 4) + n * 12,
+                        "ms": ms_build}
     for v in out.values():
         v["GBps"] = v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None
     return out
@@ -151,6 +264,7 @@ def precision(snap, theta, eps, nsample=65536, seed=40, reps=3, log=print, ref=N
     out = {"theta": theta, "eps": eps,
            "sample": f"{len(idx)} targets, seeded uniform subsample (seed {seed}) of "
                      f"{snap.n}; reference: FP64 direct sum on the GPU (tree_direct)"}
+    walks = {}
     for name, f16 in (("fp32", False), ("fp16_far", True)):
         tree = bh.Tree(snap.n, far_fp16=f16)
         tree.build(pos, mass)
@@ -165,6 +279,7 @@ def precision(snap, theta, eps, nsample=65536, seed=40, reps=3, log=print, ref=N
         tree.close()
         ea = _rel(acc[idx], ref[0])
         ep = _rel(pot[idx], ref[1])
+        walks[name] = acc[idx]
         out[name] = {"walk_ms": ms, "err_acc_median": float(np.median(ea)),
                      "err_acc_p99": float(np.percentile(ea, 99)),
                      "err_pot_median": float(np.median(ep)),
@@ -173,7 +288,11 @@ def precision(snap, theta, eps, nsample=65536, seed=40, reps=3, log=print, ref=N
         log(f"[bench] precision {name}: walk {ms:.2f} ms, acc err median "
             f"{out[name]['err_acc_median']:.2e} p99 {out[name]['err_acc_p99']:.2e}")
     out["speedup_walk_fp16_far"] = out["fp32"]["walk_ms"] / out["fp16_far"]["walk_ms"]
+    for name in ("fp32", "fp16_far"):
+        out[name]["frac_fp32_peak"] = out[name]["tflops_walk"] / PEAK_FP32_TFLOPS
     out["_ref"] = ref
+    out["_anchor"] = {"pos": snap.pos, "mass": snap.mass, "eps": eps, "idx": idx,
+                      "ref_acc": ref[0], "walks": walks}
     return out
 
 
@@ -183,12 +302,15 @@ def precision_sweep(name="disk_halo_4m", thetas=(0.3, 0.4, 0.6), log=print):
     from workloads import ics
     w = ics.WORKLOADS[name]
     snap = ics.make(name)
-    rows, ref = [], None
+    rows, ref, anchor = [], None, None
     for th in thetas:
         r = precision(snap, th, w["eps"], log=log, ref=ref)
         ref = r.pop("_ref")
+        a = r.pop("_anchor")
+        if abs(th - w["theta"]) < 1e-9:
+            anchor = a
         rows.append(r)
-    return {"workload": name, "n": snap.n, "eps": w["eps"], "rows": rows}
+    return {"workload": name, "n": snap.n, "eps": w["eps"], "rows": rows, "_anchor": anchor}
 
 
 def param_sweep(name="disk_halo_4m", thetas=(0.3, 0.4, 0.5, 0.6, 0.8),
@@ -282,6 +404,9 @@ def adjoint(name="disk_halo_1m_adjoint", log=print):
     # sweeps agree to rounding, not bit for bit
     diff = max(float((a.grad - g).abs().max() / g.abs().max())
                for a, g in zip((x0, v0, m), grads))
+    # one force VJP at the initial state, its adjoint walk kernel timed by the
+    # library's events around that launch (the counters' workload)
+    vjp_ms, vjp_inter = vjp_kernel_ms(tree, s, w)
     tree.close()
     fwd1, bwd1 = t4 - t3, t5 - t4
     snap_mb = w["steps"] * s.n * tree.snapshot_bytes(1) / 1e6
@@ -293,10 +418,178 @@ def adjoint(name="disk_halo_1m_adjoint", log=print):
             "backward_over_forward": bwd / fwd,
             "ms_per_step_forward": 1e3 * fwd / w["steps"],
             "ms_per_step_backward": 1e3 * bwd / w["steps"], "grad_finite": finite,
+            "walk_vjp_kernel_ms": vjp_ms, "walk_vjp_interactions": vjp_inter,
             "every_step_snapshots": {"forward_s": fwd1, "backward_s": bwd1,
                                      "backward_over_forward": bwd1 / fwd1,
                                      "snapshot_mb": snap_mb,
                                      "grad_max_rel_diff_vs_every_8": diff}}
+
+
+def counter_report(counters, key, tflops_paper, paper_flops_per_walk):
+    """FP32 (+ FP16) VALU flops of a walk kernel from the committed counters:
+    the counted flops relative to the paper's convention on the profiled
+    dispatch, applied to this run's rate; None without current counters."""
+    c = (counters or {}).get(key)
+    if not c or not (c.get("n_pp") or c.get("n_pc")):
+        return None
+    hw, ins = counter_flops(c)
+    ref = paper_flops(c.get("n_pp", 0), c.get("n_pc", 0))
+    tf = tflops_paper * hw / ref
+    return {"kernel": key, "tflops_counted": tf, "frac_counted": tf / PEAK_FP32_TFLOPS,
+            "tflops_fp32_instruction_classes": tflops_paper * ins / ref,
+            "counted_over_paper_flops": hw / ref,
+            "valu_instructions": c.get("SQ_INSTS_VALU"),
+            "fma_f32": c.get("SQ_INSTS_VALU_FMA_F32"), "mul_f32": c.get("SQ_INSTS_VALU_MUL_F32"),
+            "add_f32": c.get("SQ_INSTS_VALU_ADD_F32"), "trans_f32": c.get("SQ_INSTS_VALU_TRANS_F32"),
+            "flops_fp16": c.get("SQ_INSTS_VALU_FLOPS_FP16"),
+            "profiled_ms": c.get("mean_ms")}
+
+
+def vjp_kernel_ms(tree, s, w, reps=3):
+    """Adjoint walk kernel time of tree_force_vjp at the initial state of the
+    differentiation workload (mean over reps after one warm-up call), and the
+    interaction count of its lists."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    tree.set_state(torch.from_numpy(s.pos).to(dev), torch.from_numpy(s.vel).to(dev),
+                   torch.from_numpy(s.mass).to(dev))
+    u = torch.from_numpy(np.random.default_rng(77).normal(size=(s.n, 3)).astype(np.float32)).to(dev)
+    gp = torch.zeros((s.n, 3), dtype=torch.float32, device=dev)
+    gm = torch.zeros((s.n,), dtype=torch.float32, device=dev)
+    tree.force(w["theta"], w["eps"])
+    st = tree.stats()
+    ms = []
+    for k in range(reps + 1):
+        tree.force_vjp(w["theta"], w["eps"], u, 1.0, gp, gm)
+        t = tree.stats()["ms_walk_vjp"]
+        if k:
+            ms.append(t)
+    return sum(ms) / len(ms), int(st["n_pp"] + st["n_pc"])
+
+
+def profile_kernels(meta_path=None, log=print):
+    """The dispatches the committed VALU counters describe: at the 13M
+    workload one FP32 and one FP16 far-field walk after a warm-up of each;
+    at the 1M differentiation workload's initial state one force VJP after a
+    warm-up.  Writes their interaction counts to meta_path (JSON)."""
+    import numpy as np
+    import torch
+
+    import paper_1412_0659_amd as bh
+    from workloads import ics
+    dev = torch.device("cuda:0")
+    w = ics.WORKLOADS["disk_halo_13m"]
+    snap = ics.make("disk_halo_13m")
+    pos = torch.from_numpy(snap.pos).to(dev)
+    mass = torch.from_numpy(snap.mass).to(dev)
+    meta = {"workload": "disk_halo_13m", "theta": w["theta"], "eps": w["eps"], "kernels": {}}
+    for f16, key in ((False, "k_walk<false, false>"), (True, "k_walk<false, true>")):
+        t = bh.Tree(snap.n, far_fp16=f16)
+        t.build(pos, mass)
+        for _ in range(2):
+            t.force(w["theta"], w["eps"])
+            st = t.stats()
+        log(f"[bench] profile {key}: walk {st['ms_walk']:.2f} ms")
+        meta["kernels"][key] = {"n_pp": st["n_pp"], "n_pc": st["n_pc"],
+                                "workload": "disk_halo_13m"}
+        t.close()
+    del pos, mass
+    wa = ics.DIFF_WORKLOADS["disk_halo_1m_adjoint"]
+    s = ics.disk_halo_scaled(wa["n"], wa["seed"])
+    t = bh.Tree(s.n, adjoint=True, pos_fp64=True)
+    ms, inter = vjp_kernel_ms(t, s, wa, reps=1)
+    log(f"[bench] profile k_walk_vjp<false>: {ms:.2f} ms")
+    meta["kernels"]["k_walk_vjp<false>"] = {"interactions": inter,
+                                            "workload": "disk_halo_1m_adjoint"}
+    t.close()
+    if meta_path:
+        with open(meta_path, "w") as f:
+            json.dump(meta, f, indent=1)
+    return meta
+
+
+def write_counters(out_path, meta_path, dbs, command):
+    """The committed counter summary: per-dispatch counters of the profiled
+    walk and VJP kernels (the second, warm dispatch of each), the sources'
+    hashes and the profiled interaction counts."""
+    # each database holds, per walk kernel, the 13M dispatches and (FP32) one
+    # at the 1M adjoint state: keep the long ones
+    summ = pmc_summary(dbs, min_frac=0.5)
+    with open(meta_path) as f:
+        meta = json.load(f)
+    kernels = {}
+    for name, row in summ.items():
+        for key in meta["kernels"]:
+            base = key.split("<")[0]
+            if name.split("(")[0].endswith(key) or (name.startswith("void bh::" + base + "<")
+                                                     and key in name):
+                kernels[key] = dict(row, **meta["kernels"][key])
+    doc = {"command": command, "walk_source_sha256_16": walk_source_hash(),
+           "vjp_source_sha256_16": walk_source_hash(VJP_SOURCES),
+           "note": "counters are means per dispatch over the profiled dispatches, summed over "
+                   "the chip; k_walk<·> at the 13M disk + halo workload (theta 0.4, eps 0.002), "
+                   "k_walk_vjp at the 1M differentiation workload's initial state",
+           "kernels": kernels}
+    with open(out_path, "w") as f:
+        json.dump(doc, f, indent=1)
+    return doc
+
+
+def trace_summary(paths, top=30):
+    """Per-kernel calls, mean and total duration from rocprofv3 --kernel-trace
+    databases (sqlite), by total time: a text table."""
+    import sqlite3
+    from collections import defaultdict
+    tot = defaultdict(float)
+    cnt = defaultdict(int)
+    for db in paths:
+        con = sqlite3.connect(db)
+        q = ("select ks.display_name, kd.end - kd.start from rocpd_kernel_dispatch kd "
+             "join rocpd_info_kernel_symbol ks on kd.kernel_id = ks.id")
+        for name, d in con.execute(q):
+            short = name.replace("void ", "").split("(")[0].replace("bh::", "")
+            tot[short] += d
+            cnt[short] += 1
+        con.close()
+    grand = sum(tot.values())
+    lines = [f"{'kernel':44s} {'calls':>6s} {'avg_us':>11s} {'total_ms':>10s} {'pct':>6s}"]
+    for k in sorted(tot, key=lambda k: -tot[k])[:top]:
+        lines.append(f"{k[:44]:44s} {cnt[k]:6d} {tot[k] / cnt[k] / 1e3:11.1f} "
+                     f"{tot[k] / 1e6:10.2f} {100 * tot[k] / grand:6.2f}")
+    return "\n".join(lines)
+
+
+def write_traffic(out_path, fetch_db, write_db, copy_fetch_db, copy_write_db, command):
+    """The committed HBM traffic of the FP32 walk: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch, mean over the walk's dispatches) scaled by what the
+    same counters read for the plain 1 GiB device copy of --copy-calibration."""
+    key = "k_walk<false, false>"
+
+    def mean_of(db, counter, pat):
+        rows = [r for n, r in pmc_summary([db]).items() if pat in n]
+        vals = [r[counter] for r in rows if counter in r]
+        disp = sum(r["dispatches"] for r in rows)
+        return (sum(v * r["dispatches"] for v, r in zip(vals, rows)) / disp if disp else None,
+                disp)
+
+    f, nf = mean_of(fetch_db, "FETCH_SIZE", "k_walk<false, false>")
+    w_, nw = mean_of(write_db, "WRITE_SIZE", "k_walk<false, false>")
+    cf, _ = mean_of(copy_fetch_db, "FETCH_SIZE", "copyBuffer")
+    cw, _ = mean_of(copy_write_db, "WRITE_SIZE", "copyBuffer")
+    gib = float(1 << 30)
+    ff, wf = gib / (cf * 1024.0), gib / (cw * 1024.0)
+    doc = {"kernel": key, "workload": "disk_halo_13m", "walk_source_sha256_16": walk_source_hash(),
+           "fetch_size_kib_per_dispatch": f, "write_size_kib_per_dispatch": w_,
+           "dispatches": [nf, nw],
+           "copy_calibration": {"bytes_read": gib, "bytes_written": gib, "fetch_size_kib": cf,
+                                "write_size_kib": cw, "fetch_factor": ff, "write_factor": wf},
+           "hbm_bytes_per_launch": f * 1024.0 * ff + w_ * 1024.0 * wf,
+           "hbm_fetch_bytes_per_launch": f * 1024.0 * ff,
+           "hbm_write_bytes_per_launch": w_ * 1024.0 * wf, "command": command}
+    with open(out_path, "w") as fh:
+        json.dump(doc, fh, indent=1)
+    return doc
 
 
 def domains(name="disk_halo_13m", ps=(2, 4, 8, 16), curve="ph", max_boundary=4096, reps=3,
@@ -436,8 +729,41 @@ def main(argv=None):
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy five times (the "
                          "reference kernel for scaling the HBM byte counters)")
+    ap.add_argument("--no-c4", action="store_true",
+                    help="skip the 4M precision sweep over theta 0.3 / 0.4 / 0.6")
+    ap.add_argument("--no-param-sweep", action="store_true",
+                    help="skip the walk cost curve over theta, nleaf and ncrit")
+    ap.add_argument("--profile-kernels", type=str, default=None, metavar="META_JSON",
+                    help="only run the dispatches the committed VALU counters describe "
+                         "(run under rocprofv3 --pmc); write their interaction counts here")
+    ap.add_argument("--pmc-summary", nargs="+", default=None, metavar="DB",
+                    help="only print the per-kernel mean counters of rocprofv3 databases")
+    ap.add_argument("--write-counters", nargs="+", default=None, metavar="ARG",
+                    help="OUT_JSON META_JSON DB...: write the committed counter summary")
+    ap.add_argument("--trace-summary", nargs="+", default=None, metavar="DB",
+                    help="only print the per-kernel time table of rocprofv3 --kernel-trace "
+                         "databases")
+    ap.add_argument("--write-traffic", nargs=5, default=None, metavar="ARG",
+                    help="OUT_JSON FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB: write the "
+                         "committed walk traffic summary")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args(argv)
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary))
+        return 0
+    if args.pmc_summary:
+        print(json.dumps(pmc_summary(args.pmc_summary), indent=1))
+        return 0
+    if args.write_traffic:
+        out, dbs = args.write_traffic[0], args.write_traffic[1:]
+        print(json.dumps(write_traffic(out, *dbs, os.environ.get("BH_PROFILE_COMMAND", "")),
+                         indent=1))
+        return 0
+    if args.write_counters:
+        out, meta, dbs = args.write_counters[0], args.write_counters[1], args.write_counters[2:]
+        cmd = os.environ.get("BH_PROFILE_COMMAND", "")
+        print(json.dumps(write_counters(out, meta, dbs, cmd), indent=1))
+        return 0
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the "
@@ -463,11 +789,16 @@ def main(argv=None):
         return 0
 
     log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    if args.profile_kernels:
+        profile_kernels(args.profile_kernels, log=log)
+        return 0
     if args.adjoint_only:
         print(json.dumps(adjoint(log=log)))
         return 0
     if args.precision_sweep:
-        print(json.dumps(precision_sweep(log=log)))
+        r = precision_sweep(log=log)
+        r.pop("_anchor")
+        print(json.dumps(r))
         return 0
     if args.param_sweep:
         print(json.dumps(param_sweep(log=log)))
@@ -531,8 +862,6 @@ def main(argv=None):
                    if w["model"] == "disk_halo" else "Plummer sphere"},
         "tflops_step": flops / wall / 1e12,
         "tflops_walk": walk_tflops,
-        "tflops_walk_instruction_derived": (KERNEL_FLOPS_PP * n_pp + KERNEL_FLOPS_PC * n_pc)
-        / (walk_ms * 1e-3) / 1e12,
         "interactions_per_s_walk": inter / (walk_ms * 1e-3),
         "pp_per_particle": n_pp / args.steps / snap.n,
         "pc_per_particle": n_pc / args.steps / snap.n,
@@ -545,7 +874,9 @@ def main(argv=None):
                  "depth": last["depth"]},
         "hbm_phases": hbm_phases(snap.n, last["ncells"],
                                  float(np.mean([s["ms_sort"] for s in per])),
-                                 float(np.mean([s["ms_moments"] for s in per]))),
+                                 float(np.mean([s["ms_moments"] for s in per])),
+                                 ms_build=float(np.mean([s["ms_build"] for s in per])),
+                                 depth=last["depth"]),
         "paper_context": {"hardware": "NVIDIA K20X, the paper's 1-GPU column (Table II)",
                           "workload": "the paper's Milky Way model, 13M particles, theta 0.4",
                           "gravity_interactions_per_s": 3.33e10, "gravity_tflops": 1.77,
@@ -557,11 +888,46 @@ def main(argv=None):
     }
     tree.close()
     del pos, vel, mass
+    counters = load_counters()
+    out["valu_counters"] = counter_report(counters, "k_walk<false, false>", walk_tflops,
+                                          paper_flops(n_pp, n_pc) / args.steps)
+    anchors = []
     if not args.no_precision:
         out["precision"] = precision(snap, theta, eps, log=log)
         out["precision"].pop("_ref")
+        a = out["precision"].pop("_anchor")
+        a["name"] = f"{args.workload} theta {theta}"
+        anchors.append(a)
+        f16 = out["precision"]["fp16_far"]
+        f16["valu_counters"] = counter_report(counters, "k_walk<false, true>", f16["tflops_walk"],
+                                              paper_flops(f16["n_pp"], f16["n_pc"]))
+    if not args.no_c4:
+        c4 = precision_sweep(log=log)
+        a = c4.pop("_anchor")
+        if a is not None:
+            a["name"] = f"{c4['workload']} theta 0.4"
+            anchors.append(a)
+        out["precision_c4"] = c4
+    if not args.no_param_sweep:
+        out["param_sweep"] = param_sweep(log=log)
     if not args.no_adjoint:
         out["adjoint"] = adjoint(log=log)
+        ad = out["adjoint"]
+        c = (counters or {}).get("k_walk_vjp<false>")
+        rep = None
+        if c and c.get("interactions"):
+            hw, ins = counter_flops(c)
+            # the counted flops per interaction of the profiled dispatch, applied
+            # to this run's lists and kernel time
+            per = hw / c["interactions"]
+            tf = per * ad["walk_vjp_interactions"] / (ad["walk_vjp_kernel_ms"] * 1e-3) / 1e12
+            rep = {"kernel": "k_walk_vjp", "bound": "alu", "achieved": tf,
+                   "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": tf / PEAK_FP32_TFLOPS,
+                   "counter_flops_per_interaction": per,
+                   "instruction_flops_per_interaction": ins / c["interactions"],
+                   "convention": "hardware FP32 VALU flop counters (SQ_INSTS_VALU_FLOPS_FP32 "
+                                 "+ _TRANS, x 64 lanes) of the profiled dispatch per interaction"}
+        ad["roofline_walk_vjp"] = rep
     if not args.no_domains:
         r = domains(args.workload, (8,), args.curve, log=log, snap=snap)
         row = r["rows"][0]
@@ -580,6 +946,9 @@ def main(argv=None):
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(snap, theta, eps)
+        if anchors:
+            log("[bench] oracle anchors of the force errors ...")
+            out["cpu_baseline"]["oracle_anchors"] = oracle_anchors(anchors)
     out["ms_phase"] = {k: float(v) for k, v in out["ms_phase"].items()}
     print(json.dumps(out))
     return 0

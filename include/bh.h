@@ -265,6 +265,7 @@ typedef struct bh_stats {
     double ms_moments;    /* moment pass of the last build */
     double ms_walk;       /* walk kernel of the last force evaluation */
     double ms_step;       /* whole last leapfrog_step (0 if none) */
+    double ms_walk_vjp;   /* adjoint walk kernel of the last tree_force_vjp (0 if none) */
 } bh_stats;
 
 /* Fill *out (host).  Synchronises s and reports latched device status. */

@@ -60,7 +60,8 @@ class bh_stats(ctypes.Structure):
                 ("ngroups", ctypes.c_int64), ("depth", ctypes.c_int64), ("n_pp", ctypes.c_int64),
                 ("n_pc", ctypes.c_int64), ("ms_sort", ctypes.c_double),
                 ("ms_build", ctypes.c_double), ("ms_moments", ctypes.c_double),
-                ("ms_walk", ctypes.c_double), ("ms_step", ctypes.c_double)]
+                ("ms_walk", ctypes.c_double), ("ms_step", ctypes.c_double),
+                ("ms_walk_vjp", ctypes.c_double)]
 
 
 SYMBOLS = ["bh_create", "bh_destroy", "tree_build", "bh_set_state", "tree_force",

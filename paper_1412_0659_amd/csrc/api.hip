@@ -576,6 +576,7 @@ int bh_stats_get(bh_ctx *c, bh_stats *out, hipStream_t s) {
     out->ms_moments = elapsed(c, 2, 3);
     out->ms_walk = elapsed(c, 4, 5);
     out->ms_step = elapsed(c, 6, 7);
+    out->ms_walk_vjp = elapsed(c, 8, 9);
     return check_status(c);
 }
 

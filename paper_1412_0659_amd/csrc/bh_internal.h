@@ -177,9 +177,9 @@ struct bh_ctx {
     int forced_grid_levels = -1;    // test hook: levels split by the grid kernels
 
     // events: build start, after sort, after octree+groups, after moments,
-    // walk start, walk end, step start, step end
-    hipEvent_t ev[8]{};
-    bool ev_rec[8]{};
+    // walk start, walk end, step start, step end, adjoint walk start, end
+    hipEvent_t ev[10]{};
+    bool ev_rec[10]{};
     std::string last_error;
 };
 

@@ -457,10 +457,12 @@ void launch_walk_vjp(bh_ctx *c, float eps, const float *u, float coef, float *g_
     a.cap = cap; a.nmax = nmax;
     a.eps2 = eps * eps;
     hipLaunchKernelGGL(k_reset_work_vjp, dim3(1), dim3(64), 0, st, c->work);
+    record_event(c, 8, st);
     if (eps == 0.f)
         hipLaunchKernelGGL(k_walk_vjp<true>, dim3(c->walk_grid), dim3(64), 0, st, a);
     else
         hipLaunchKernelGGL(k_walk_vjp<false>, dim3(c->walk_grid), dim3(64), 0, st, a);
+    record_event(c, 9, st);
     hipLaunchKernelGGL(k_fold_xcd, dim3(2048), dim3(256), 0, st, c->lcell, (uint64_t)0, 10u, cap,
                        lstride, ls);
     hipLaunchKernelGGL(k_fold_xcd, dim3(grid), dim3(256), 0, st, c->gsrc, (uint64_t)n, 4u, nmax,
