@@ -79,27 +79,108 @@ def counter_flops(c):
     return hw, ins
 
 
+def pmc_rows(db):
+    """Every dispatch of a rocprofv3 --pmc output database (sqlite) in launch
+    order: [{"kernel": name, "ms": duration, counter: value, ...}]."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    q = ("select ks.display_name, kd.id, ip.name, sum(pe.value), kd.end - kd.start "
+         "from rocpd_pmc_event pe join rocpd_info_pmc ip on pe.pmc_id = ip.id "
+         "join rocpd_kernel_dispatch kd on pe.event_id = kd.event_id "
+         "join rocpd_info_kernel_symbol ks on kd.kernel_id = ks.id group by kd.id, ip.name "
+         "order by kd.id")
+    rows = {}
+    for name, did, cname, val, d in con.execute(q):
+        r = rows.setdefault(did, {"kernel": name, "ms": d / 1e6})
+        r[cname] = val
+    con.close()
+    return [rows[k] for k in sorted(rows)]
+
+
 def pmc_dispatches(paths):
     """Counter values of every dispatch in rocprofv3 --pmc output databases
     (sqlite): {kernel: [{counter: value, "ms": duration}, ...]}."""
-    import sqlite3
     from collections import defaultdict
     out = defaultdict(list)
     for db in paths:
-        con = sqlite3.connect(db)
-        q = ("select ks.display_name, kd.id, ip.name, sum(pe.value), kd.end - kd.start "
-             "from rocpd_pmc_event pe join rocpd_info_pmc ip on pe.pmc_id = ip.id "
-             "join rocpd_kernel_dispatch kd on pe.event_id = kd.event_id "
-             "join rocpd_info_kernel_symbol ks on kd.kernel_id = ks.id group by kd.id, ip.name "
-             "order by kd.id")
-        rows = {}
-        for name, did, cname, val, d in con.execute(q):
-            r = rows.setdefault(did, {"kernel": name, "ms": d / 1e6})
-            r[cname] = val
-        con.close()
-        for r in rows.values():
+        for r in pmc_rows(db):
+            r = dict(r)
             out[r.pop("kernel")].append(r)
     return out
+
+
+def build_phase_counters(db, counter, build_index=1):
+    """Sum of one counter over the kernels of each phase of one tree build in
+    a --pmc database: the build_index-th build (a build starts at a
+    k_bbox_partial dispatch); sort = through k_gather, build = up to the
+    first moments kernel, moments = the k_moments_ kernels."""
+    rows = pmc_rows(db)
+    starts = [i for i, r in enumerate(rows) if "k_bbox_partial" in r["kernel"]]
+    i = starts[build_index]
+    out = {"sort": 0.0, "build": 0.0, "moments": 0.0}
+    phase = "sort"
+    kernels = {k: [] for k in out}
+    for r in rows[i:]:
+        name = r["kernel"]
+        if phase == "moments" and "k_moments_" not in name:
+            break
+        if "k_moments_" in name:
+            phase = "moments"
+        out[phase] += r.get(counter, 0.0)
+        short = name.replace("void ", "").split("(")[0].replace("bh::", "")
+        if short not in kernels[phase]:
+            kernels[phase].append(short)
+        if "k_gather" in name:
+            phase = "build"
+    return out, kernels
+
+
+def write_build_traffic(out_path, fetch_db, write_db, bench_json, command):
+    """HBM bytes of the tree-build phases of the first leapfrog step's
+    rebuild: FETCH_SIZE and WRITE_SIZE (KiB) scaled by the copy calibration
+    of the committed walk traffic file, against the algorithmic bytes of
+    hbm_phases for the tree of the bench line in bench_json."""
+    with open(TRAFFIC_FILE) as f:
+        cal = json.load(f)["copy_calibration"]
+    ff, wf = cal["fetch_factor"], cal["write_factor"]
+    fetch, kernels = build_phase_counters(fetch_db, "FETCH_SIZE")
+    write, _ = build_phase_counters(write_db, "WRITE_SIZE")
+    with open(bench_json) as f:
+        line = json.loads([l for l in f if l.startswith("{")][-1])
+    n, tree, ms = line["config"]["n"], line["tree"], line["ms_phase"]
+    alg = hbm_phases(n, tree["cells"], ms["sort"], ms["moments"], ms_build=ms["build"],
+                     depth=tree["depth"])
+    hdr = [f"# HBM bytes of the tree rebuild of the first leapfrog step at {line['config']['workload']}"
+           f" ({n} particles, {tree['cells']} cells),",
+           f"# from rocprofv3 counters: FETCH_SIZE x {ff:.3f} + WRITE_SIZE x {wf:.3f} (the factors a plain"
+           " 1 GiB device copy reads for the same counters), summed over each phase's kernels of"
+           " that build (particles already nearly in key order).",
+           "# ms: the bench line's mean phase time (events, no profiler); GB/s = counted bytes / ms.",
+           f"# commands: {command}",
+           "#",
+           f"{'phase':9s} {'fetch_MB':>9s} {'write_MB':>9s} {'total_MB':>9s} {'algorithmic_MB':>15s}"
+           f" {'ratio':>6s} {'ms':>7s} {'GB/s':>8s}  kernels"]
+    rows = []
+    for ph in ("sort", "build", "moments"):
+        f_b = fetch[ph] * 1024.0 * ff
+        w_b = write[ph] * 1024.0 * wf
+        a_b = alg[ph]["bytes"] if ph in alg else None
+        t = ms[ph]
+        rows.append(f"{ph:9s} {f_b / 1e6:9.1f} {w_b / 1e6:9.1f} {(f_b + w_b) / 1e6:9.1f} "
+                    f"{(a_b / 1e6 if a_b else float('nan')):15.1f} "
+                    f"{((f_b + w_b) / a_b if a_b else float('nan')):6.2f} {t:7.3f} "
+                    f"{(f_b + w_b) / (t * 1e-3) / 1e9:8.1f}  {', '.join(kernels[ph])}")
+    foot = ["#",
+            "# algorithmic bytes (hbm_phases): sort 376 B per particle (box 12, keys 24, 8 radix",
+            "# passes x 32, gather 84); build: the keys read once per splitting level plus 40 B per",
+            "# cell and 12 B per particle for the groups (what a per-level scan would move; the",
+            "# build's binary searches over cell ranges read less); moments: 16 B per particle +",
+            "# 260 B per cell (topology 20, FP64 M, S, Q written 80 and read by the parent 80, walk",
+            "# records 80)."]
+    text = "\n".join(hdr + rows + foot) + "\n"
+    with open(out_path, "w") as f:
+        f.write(text)
+    return text
 
 
 def pmc_summary(paths, min_frac=0.0):
@@ -207,13 +288,14 @@ def hbm_phases(n, ncells, ms_sort, ms_moments, pos_fp64=False, ms_build=None, de
     + 12 B written (scatter); gather 4 B index + 32 B state read, 32 B state +
     16 B (x, y, z, m) record written (+48 B with the FP64 master).
     Moments: 16 B per particle
-    read plus, per cell, 16 B of topology read, 104 B of FP64 moments written
-    and read back by the parent pass and 80 B of walk records written.
+    read plus, per cell, 20 B of topology read (nchild, first, count, key
+    prefix), 80 B of FP64 moments (M, S, Q) written and read back by the
+    parent's pass and 80 B of walk records written.
     Build (with ms_build and depth): 8 B of keys per particle per splitting
     level, 36 B written and 4 B read per cell, 12 B per particle for the groups."""
     gather = 4 + 32 + 32 + 16 + (48 if pos_fp64 else 0)
     sort_b = n * (12 + 24 + 8 * 32 + gather)
-    mom_b = n * 16 + ncells * (16 + 104 + 104 + 80)
+    mom_b = n * 16 + ncells * (20 + 80 + 80 + 80)
     out = {"sort": {"bytes": sort_b, "ms": ms_sort},
            "moments": {"bytes": mom_b, "ms": ms_moments}}
     if ms_build is not None and depth is not None:
@@ -746,6 +828,9 @@ def main(argv=None):
     ap.add_argument("--write-traffic", nargs=5, default=None, metavar="ARG",
                     help="OUT_JSON FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB: write the "
                          "committed walk traffic summary")
+    ap.add_argument("--write-build-traffic", nargs=4, default=None,
+                    metavar=("OUT", "FETCH_DB", "WRITE_DB", "BENCH_JSON"),
+                    help="write the build-phase HBM bytes summary from two --pmc runs")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args(argv)
     if args.trace_summary:
@@ -758,6 +843,10 @@ def main(argv=None):
         out, dbs = args.write_traffic[0], args.write_traffic[1:]
         print(json.dumps(write_traffic(out, *dbs, os.environ.get("BH_PROFILE_COMMAND", "")),
                          indent=1))
+        return 0
+    if args.write_build_traffic:
+        out, f_db, w_db, bj = args.write_build_traffic
+        print(write_build_traffic(out, f_db, w_db, bj, os.environ.get("BH_PROFILE_COMMAND", "")))
         return 0
     if args.write_counters:
         out, meta, dbs = args.write_counters[0], args.write_counters[1], args.write_counters[2:]

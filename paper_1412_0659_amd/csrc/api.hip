@@ -607,7 +607,10 @@ int bh_export(bh_ctx *c, int array, void *dst, int64_t cap_bytes, int64_t *nbyte
         case BH_ARR_CELL_NCHILD: src = q.nchild; bytes = 4 * nc; break;
         case BH_ARR_CELL_PARENT: src = q.parent; bytes = 4 * nc; break;
         case BH_ARR_MOM_M: src = q.M; bytes = 8 * nc; break;
-        case BH_ARR_MOM_COM: src = q.com; bytes = 24 * nc; break;
+        case BH_ARR_MOM_COM:
+            launch_com(c, s);
+            BH_HIP(c, hipStreamSynchronize(s));
+            src = q.com; bytes = 24 * nc; break;
         case BH_ARR_MOM_Q: src = q.Q; bytes = 48 * nc; break;
         case BH_ARR_CELL_COMF: src = q.wA; bytes = 16 * nc; break;
         case BH_ARR_CELL_SIZE: src = q.size; bytes = 8 * nc; break;

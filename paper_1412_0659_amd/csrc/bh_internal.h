@@ -47,7 +47,7 @@ struct Cells {
     uint32_t *part;    // [kBuildGrid + 1] per-block partials of the level scans
     uint32_t *lbt;     // [8^kTableLevel + 1] first sorted slot of every level-kTableLevel prefix
     // FP64 moments of the upward pass
-    double *M, *S, *com, *Q;  // [c], [c][3], [c][3], [c][6]
+    double *M, *S, *com, *Q;  // [c], [c][3], [c][3], [c][6]; com = S / M, filled for export
     // records read by the walk
     float4 *wA;  // com (FP32) and r_open^2 of the last theta
     uint2 *wN;   // internal: (child0, nchild); leaf: (begin, count | kLeafBit)
@@ -222,6 +222,7 @@ void launch_groups(bh_ctx *c, uint32_t n, hipStream_t st);
 
 // moments.hip
 void launch_moments(bh_ctx *c, hipStream_t st, int grid_levels);
+void launch_com(bh_ctx *c, hipStream_t st);
 void launch_walk_prep(bh_ctx *c, float theta, hipStream_t st);
 
 // let.hip: boundary trees and local essential trees (Sec. III.B.2); nc is

@@ -9,9 +9,11 @@
 //
 // Each cell is one thread summing in a fixed order (a leaf over its
 // particles in sorted order, a parent over its children in child order),
-// with contraction off, so the result does not depend on the launch.  Leaves
-// first, then internal cells level by level from the deepest.  The walk
-// reads FP32 copies: com and the opening radius
+// with contraction off, so the result does not depend on the launch.  Level
+// by level from the deepest, leaves and parents of a level in one pass that
+// also writes the cell's walk records.  The FP64 record of a cell is M, S
+// and Q (80 bytes, read once more by its parent); com = S / M is recomputed
+// where needed.  The walk reads FP32 copies: com and the opening radius
 // r_open = l / theta + |com - geometric centre| (l = cell size) for the
 // opening test, and (com, M, -3 Q, tr Q / 2, -3 tr Q / 2) for the
 // particle-cell terms.
@@ -25,61 +27,47 @@ namespace bh {
 // The sums run in the same order either way.
 constexpr uint32_t kStage = 16;
 
-__global__ __launch_bounds__(256) void k_moments_leaf(Cells c, const float *__restrict__ x,
-                                                      const float *__restrict__ y,
-                                                      const float *__restrict__ z,
-                                                      const float *__restrict__ m) {
-    uint32_t nc = c.ls[kLevels];
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) {
-        if (c.nchild[i] != 0) continue;
-        const uint32_t b = c.begin[i], cnt = c.count[i], e = b + cnt;
-        double mm = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        double q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0;
-        double c0, c1, c2;
-        if (cnt <= kStage) {
-            float px[kStage], py[kStage], pz[kStage], pm[kStage];
+struct MomArgs {
+    Cells c;
+    const float *x, *y, *z, *m;
+    const float *box;  // lo xyz, side
+    int curve;
+};
+
+struct Mom {
+    double M, s0, s1, s2, q0, q1, q2, q3, q4, q5;
+};
+
+template <bool kStaged>
+__device__ __forceinline__ void leaf_sums(const MomArgs &a, uint32_t b, uint32_t cnt, Mom &r,
+                                          double &c0, double &c1, double &c2) {
+    const uint32_t e = b + cnt;
+    double mm = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    double q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0;
+    if (kStaged && cnt <= kStage) {
+        float px[kStage], py[kStage], pz[kStage], pm[kStage];
 #pragma unroll
-            for (uint32_t k = 0; k < kStage; ++k) {
-                const uint32_t j = k < cnt ? b + k : b;
-                px[k] = x[j]; py[k] = y[j]; pz[k] = z[j]; pm[k] = m[j];
-            }
+        for (uint32_t k = 0; k < kStage; ++k) {
+            const uint32_t j = k < cnt ? b + k : b;
+            px[k] = a.x[j]; py[k] = a.y[j]; pz[k] = a.z[j]; pm[k] = a.m[j];
+        }
 #pragma unroll
-            for (uint32_t k = 0; k < kStage; ++k) {
-                if (k < cnt) {
-                    const double mj = pm[k];
-                    mm = mm + mj;
-                    s0 = s0 + mj * (double)px[k];
-                    s1 = s1 + mj * (double)py[k];
-                    s2 = s2 + mj * (double)pz[k];
-                }
-            }
-            c0 = s0 / mm; c1 = s1 / mm; c2 = s2 / mm;
-#pragma unroll
-            for (uint32_t k = 0; k < kStage; ++k) {
-                if (k < cnt) {
-                    const double mj = pm[k];
-                    const double d0 = (double)px[k] - c0, d1 = (double)py[k] - c1,
-                                 d2 = (double)pz[k] - c2;
-                    q0 = q0 + (mj * d0) * d0;
-                    q1 = q1 + (mj * d1) * d1;
-                    q2 = q2 + (mj * d2) * d2;
-                    q3 = q3 + (mj * d0) * d1;
-                    q4 = q4 + (mj * d0) * d2;
-                    q5 = q5 + (mj * d1) * d2;
-                }
-            }
-        } else {
-            for (uint32_t j = b; j < e; ++j) {
-                double mj = m[j];
+        for (uint32_t k = 0; k < kStage; ++k) {
+            if (k < cnt) {
+                const double mj = pm[k];
                 mm = mm + mj;
-                s0 = s0 + mj * (double)x[j];
-                s1 = s1 + mj * (double)y[j];
-                s2 = s2 + mj * (double)z[j];
+                s0 = s0 + mj * (double)px[k];
+                s1 = s1 + mj * (double)py[k];
+                s2 = s2 + mj * (double)pz[k];
             }
-            c0 = s0 / mm; c1 = s1 / mm; c2 = s2 / mm;
-            for (uint32_t j = b; j < e; ++j) {
-                double mj = m[j];
-                double d0 = (double)x[j] - c0, d1 = (double)y[j] - c1, d2 = (double)z[j] - c2;
+        }
+        c0 = s0 / mm; c1 = s1 / mm; c2 = s2 / mm;
+#pragma unroll
+        for (uint32_t k = 0; k < kStage; ++k) {
+            if (k < cnt) {
+                const double mj = pm[k];
+                const double d0 = (double)px[k] - c0, d1 = (double)py[k] - c1,
+                             d2 = (double)pz[k] - c2;
                 q0 = q0 + (mj * d0) * d0;
                 q1 = q1 + (mj * d1) * d1;
                 q2 = q2 + (mj * d2) * d2;
@@ -88,20 +76,34 @@ __global__ __launch_bounds__(256) void k_moments_leaf(Cells c, const float *__re
                 q5 = q5 + (mj * d1) * d2;
             }
         }
-        c.M[i] = mm;
-        c.S[3 * i] = s0; c.S[3 * i + 1] = s1; c.S[3 * i + 2] = s2;
-        c.com[3 * i] = c0; c.com[3 * i + 1] = c1; c.com[3 * i + 2] = c2;
-        double *q = c.Q + 6 * (size_t)i;
-        q[0] = q0; q[1] = q1; q[2] = q2; q[3] = q3; q[4] = q4; q[5] = q5;
+    } else {
+        for (uint32_t j = b; j < e; ++j) {
+            double mj = a.m[j];
+            mm = mm + mj;
+            s0 = s0 + mj * (double)a.x[j];
+            s1 = s1 + mj * (double)a.y[j];
+            s2 = s2 + mj * (double)a.z[j];
+        }
+        c0 = s0 / mm; c1 = s1 / mm; c2 = s2 / mm;
+        for (uint32_t j = b; j < e; ++j) {
+            double mj = a.m[j];
+            double d0 = (double)a.x[j] - c0, d1 = (double)a.y[j] - c1, d2 = (double)a.z[j] - c2;
+            q0 = q0 + (mj * d0) * d0;
+            q1 = q1 + (mj * d1) * d1;
+            q2 = q2 + (mj * d2) * d2;
+            q3 = q3 + (mj * d0) * d1;
+            q4 = q4 + (mj * d0) * d2;
+            q5 = q5 + (mj * d1) * d2;
+        }
     }
+    r = Mom{mm, s0, s1, s2, q0, q1, q2, q3, q4, q5};
 }
 
-// A parent reads the mass and first moments of its (at most eight) children
-// at once, then sums them in child order.
-__device__ __forceinline__ void up_cell(const Cells &c, uint32_t i) {
-    const uint32_t nch = c.nchild[i];
-    if (nch == 0) return;
-    const uint32_t k0 = c.child0[i];
+// A parent reads the mass, first and second moments of its (at most eight)
+// children at once, then sums them in child order; a child's centre of mass
+// is its S / M, the same division that made it.
+__device__ __forceinline__ void parent_sums(const Cells &c, uint32_t k0, uint32_t nch, Mom &r,
+                                            double &c0, double &c1, double &c2) {
     double cm[8], cs0[8], cs1[8], cs2[8];
 #pragma unroll
     for (uint32_t k = 0; k < 8; ++k) {
@@ -118,14 +120,14 @@ __device__ __forceinline__ void up_cell(const Cells &c, uint32_t i) {
             s2 = s2 + cs2[k];
         }
     }
-    double c0 = s0 / mm, c1 = s1 / mm, c2 = s2 / mm;
+    c0 = s0 / mm; c1 = s1 / mm; c2 = s2 / mm;
     double q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0, q5 = 0;
 #pragma unroll
     for (uint32_t k = 0; k < 8; ++k) {
         if (k < nch) {
             const uint32_t j = k0 + k;
             const double mk = cm[k];
-            double d0 = c.com[3 * j] - c0, d1 = c.com[3 * j + 1] - c1, d2 = c.com[3 * j + 2] - c2;
+            const double d0 = cs0[k] / mk - c0, d1 = cs1[k] / mk - c1, d2 = cs2[k] / mk - c2;
             const double *qk = c.Q + 6 * (size_t)j;
             q0 = q0 + (qk[0] + (mk * d0) * d0);
             q1 = q1 + (qk[1] + (mk * d1) * d1);
@@ -135,27 +137,7 @@ __device__ __forceinline__ void up_cell(const Cells &c, uint32_t i) {
             q5 = q5 + (qk[5] + (mk * d1) * d2);
         }
     }
-    c.M[i] = mm;
-    c.S[3 * i] = s0; c.S[3 * i + 1] = s1; c.S[3 * i + 2] = s2;
-    c.com[3 * i] = c0; c.com[3 * i + 1] = c1; c.com[3 * i + 2] = c2;
-    double *q = c.Q + 6 * (size_t)i;
-    q[0] = q0; q[1] = q1; q[2] = q2; q[3] = q3; q[4] = q4; q[5] = q5;
-}
-
-__global__ __launch_bounds__(256) void k_moments_up(Cells c, int l) {
-    uint32_t first = c.ls[l], last = c.ls[l + 1];
-    for (uint32_t i = first + blockIdx.x * 256 + threadIdx.x; i < last; i += gridDim.x * 256)
-        up_cell(c, i);
-}
-
-// Levels 20 down to l1 in one workgroup (the deep end of the tree, few or no
-// internal cells), the same per-cell sums as k_moments_up.
-__global__ __launch_bounds__(1024) void k_moments_tail(Cells c, int l1) {
-    for (int l = kLevels - 2; l >= l1; --l) {
-        const uint32_t first = c.ls[l], last = c.ls[l + 1];
-        for (uint32_t i = first + threadIdx.x; i < last; i += 1024) up_cell(c, i);
-        __syncthreads();  // the next level up reads these cells
-    }
+    r = Mom{mm, s0, s1, s2, q0, q1, q2, q3, q4, q5};
 }
 
 // corner coordinates of a cell from its key prefix (x the high bit of each digit)
@@ -170,49 +152,99 @@ __device__ __forceinline__ void cell_coords(uint64_t prefix, uint32_t lev, uint3
     p[0] = a; p[1] = b; p[2] = d;
 }
 
-__global__ __launch_bounds__(256) void k_moments_final(Cells c, const float *__restrict__ box,
-                                                       int curve) {
-    uint32_t nc = c.ls[kLevels];
-    double lo0 = box[0], lo1 = box[1], lo2 = box[2], side = box[3];
-    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) {
-        uint32_t lev = c.level[i];
-        uint32_t p[3];
-        cell_coords(c.prefix[i], lev, p);     // the digits, deinterleaved
-        if (curve == 1) ph_decode(p, (int)lev);  // Peano-Hilbert prefix -> octant
-        double lc = side * (1.0 / (double)(1u << lev));
-        double c0 = c.com[3 * i], c1 = c.com[3 * i + 1], c2 = c.com[3 * i + 2];
-        double e0 = c0 - (lo0 + ((double)p[0] + 0.5) * lc);
-        double e1 = c1 - (lo1 + ((double)p[1] + 0.5) * lc);
-        double e2 = c2 - (lo2 + ((double)p[2] + 0.5) * lc);
-        double dl = __dsqrt_rn((e0 * e0 + e1 * e1) + e2 * e2);
-        const double *q = c.Q + 6 * (size_t)i;
-        double tr = (q[0] + q[1]) + q[2];
-        c.wA[i] = make_float4((float)c0, (float)c1, (float)c2, 0.f);
-        c.P0[i] = make_float4((float)c0, (float)c1, (float)c2, (float)c.M[i]);
-        c.P1[i] = make_float4((float)(-3.0 * q[0]), (float)(-3.0 * q[1]), (float)(-3.0 * q[2]),
-                              (float)(-3.0 * q[3]));
-        c.P2[i] = make_float4((float)(-3.0 * q[4]), (float)(-3.0 * q[5]), (float)(0.5 * tr),
-                              (float)(-1.5 * tr));
-        uint32_t nch = c.nchild[i];
-        c.wN[i] = nch ? make_uint2(c.child0[i], nch) : make_uint2(c.begin[i], c.count[i] | kLeafBit);
-        c.size[i] = make_float2((float)lc, (float)dl);
+// Cell i of level lev: its FP64 moments (M, S, Q; the centre of mass is
+// S / M wherever it is needed) and its walk records.  kStaged: small leaves
+// through registers (more VGPRs).
+template <bool kStaged>
+__device__ __forceinline__ void cell_pass(const MomArgs &a, uint32_t i, uint32_t lev) {
+    const Cells &c = a.c;
+    const uint32_t nch = c.nchild[i];
+    Mom r;
+    double c0, c1, c2;
+    uint32_t first, cnt;
+    if (nch == 0) {
+        first = c.begin[i];
+        cnt = c.count[i];
+        leaf_sums<kStaged>(a, first, cnt, r, c0, c1, c2);
+    } else {
+        first = c.child0[i];
+        cnt = nch;
+        parent_sums(c, first, nch, r, c0, c1, c2);
+    }
+    c.M[i] = r.M;
+    c.S[3 * i] = r.s0; c.S[3 * i + 1] = r.s1; c.S[3 * i + 2] = r.s2;
+    double *q = c.Q + 6 * (size_t)i;
+    q[0] = r.q0; q[1] = r.q1; q[2] = r.q2; q[3] = r.q3; q[4] = r.q4; q[5] = r.q5;
+
+    // walk records: com (FP32), opening-radius terms, particle-cell record
+    const double lo0 = a.box[0], lo1 = a.box[1], lo2 = a.box[2], side = a.box[3];
+    uint32_t p[3];
+    cell_coords(c.prefix[i], lev, p);     // the digits, deinterleaved
+    if (a.curve == 1) ph_decode(p, (int)lev);  // Peano-Hilbert prefix -> octant
+    const double lc = side * (1.0 / (double)(1u << lev));
+    const double e0 = c0 - (lo0 + ((double)p[0] + 0.5) * lc);
+    const double e1 = c1 - (lo1 + ((double)p[1] + 0.5) * lc);
+    const double e2 = c2 - (lo2 + ((double)p[2] + 0.5) * lc);
+    const double dl = __dsqrt_rn((e0 * e0 + e1 * e1) + e2 * e2);
+    const double tr = (r.q0 + r.q1) + r.q2;
+    c.wA[i] = make_float4((float)c0, (float)c1, (float)c2, 0.f);
+    c.P0[i] = make_float4((float)c0, (float)c1, (float)c2, (float)r.M);
+    c.P1[i] = make_float4((float)(-3.0 * r.q0), (float)(-3.0 * r.q1), (float)(-3.0 * r.q2),
+                          (float)(-3.0 * r.q3));
+    c.P2[i] = make_float4((float)(-3.0 * r.q4), (float)(-3.0 * r.q5), (float)(0.5 * tr),
+                          (float)(-1.5 * tr));
+    c.wN[i] = nch ? make_uint2(first, cnt) : make_uint2(first, cnt | kLeafBit);
+    c.size[i] = make_float2((float)lc, (float)dl);
+}
+
+__global__ __launch_bounds__(256) void k_moments_level(MomArgs a, int l) {
+    const uint32_t first = a.c.ls[l], last = a.c.ls[l + 1];
+    for (uint32_t i = first + blockIdx.x * 256 + threadIdx.x; i < last; i += gridDim.x * 256)
+        cell_pass<true>(a, i, (uint32_t)l);
+}
+
+// Levels 20 down to l1 in one workgroup (the deep end of the tree, few or no
+// cells), the same per-cell sums as k_moments_level (leaves read twice).
+__global__ __launch_bounds__(1024) void k_moments_tail(MomArgs a, int l1) {
+    for (int l = kLevels - 2; l >= l1; --l) {
+        const uint32_t first = a.c.ls[l], last = a.c.ls[l + 1];
+        for (uint32_t i = first + threadIdx.x; i < last; i += 1024)
+            cell_pass<false>(a, i, (uint32_t)l);
+        __syncthreads();  // the next level up reads these cells
     }
 }
 
-// Internal cells of levels grid_levels .. 20 by k_moments_tail, the levels
-// above by one grid launch each.
+// One pass per level from the deepest (leaves from their particles, parents
+// from their children, each cell's walk records as soon as its moments are
+// known): level 21 and the levels above grid_levels by one grid launch
+// each, the levels between by k_moments_tail.
 void launch_moments(bh_ctx *ctx, hipStream_t st, int grid_levels) {
     const State &s = ctx->st[ctx->cur];
-    Cells &c = ctx->cells;
-    hipLaunchKernelGGL(k_moments_leaf, dim3(kGrid * 2), dim3(256), 0, st, c,
-                       (const float *)s.x, (const float *)s.y, (const float *)s.z,
-                       (const float *)s.m);
+    MomArgs a;
+    a.c = ctx->cells;
+    a.x = s.x; a.y = s.y; a.z = s.z; a.m = s.m;
+    a.box = ctx->box;
+    a.curve = (int)ctx->p.curve;
     const int L = grid_levels < 0 ? 0 : (grid_levels > kLevels - 1 ? kLevels - 1 : grid_levels);
-    if (L < kLevels - 1) hipLaunchKernelGGL(k_moments_tail, dim3(1), dim3(1024), 0, st, c, L);
+    hipLaunchKernelGGL(k_moments_level, dim3(kGrid), dim3(256), 0, st, a, kLevels - 1);
+    if (L < kLevels - 1) hipLaunchKernelGGL(k_moments_tail, dim3(1), dim3(1024), 0, st, a, L);
     for (int l = L - 1; l >= 0; --l)
-        hipLaunchKernelGGL(k_moments_up, dim3(kGrid), dim3(256), 0, st, c, l);
-    hipLaunchKernelGGL(k_moments_final, dim3(kGrid * 2), dim3(256), 0, st, c,
-                       (const float *)ctx->box, (int)ctx->p.curve);
+        hipLaunchKernelGGL(k_moments_level, dim3(kGrid), dim3(256), 0, st, a, l);
+}
+
+// com = S / M of every cell (FP64), for export
+__global__ __launch_bounds__(256) void k_com(Cells c) {
+    const uint32_t nc = c.ls[kLevels];
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) {
+        const double mm = c.M[i];
+        c.com[3 * i] = c.S[3 * i] / mm;
+        c.com[3 * i + 1] = c.S[3 * i + 1] / mm;
+        c.com[3 * i + 2] = c.S[3 * i + 2] / mm;
+    }
+}
+
+void launch_com(bh_ctx *ctx, hipStream_t st) {
+    hipLaunchKernelGGL(k_com, dim3(kGrid * 2), dim3(256), 0, st, ctx->cells);
 }
 
 // r_open^2 = (fl32(l / theta) + delta)^2 in FP32, stored in wA.w

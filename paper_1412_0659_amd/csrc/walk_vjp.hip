@@ -404,8 +404,8 @@ __global__ __launch_bounds__(256) void k_moments_vjp(Cells c, const float4 *__re
         const double qxx = l[4 * cap], qyy = l[5 * cap], qzz = l[6 * cap], qxy = l[7 * cap],
                      qxz = l[8 * cap], qyz = l[9 * cap];
         const double M = c.M[cc];
-        const double sx = xk - c.com[3 * (size_t)cc], sy = yk - c.com[3 * (size_t)cc + 1],
-                     sz = zk - c.com[3 * (size_t)cc + 2];
+        const double sx = xk - c.S[3 * (size_t)cc] / M, sy = yk - c.S[3 * (size_t)cc + 1] / M,
+                     sz = zk - c.S[3 * (size_t)cc + 2] / M;
         const double Lx = 2.0 * qxx * sx + qxy * sy + qxz * sz;
         const double Ly = qxy * sx + 2.0 * qyy * sy + qyz * sz;
         const double Lz = qxz * sx + qyz * sy + 2.0 * qzz * sz;
