@@ -378,6 +378,36 @@ def precision(snap, theta, eps, nsample=65536, seed=40, reps=3, log=print, ref=N
     return out
 
 
+def paired_sets(snap, theta, eps, ref, idx, base_ms, caps=(32, 48, 64), reps=3, log=print):
+    """Paired target sets (pair_groups = cap: sibling groups of together at
+    most cap particles walked as one): walk time, interactions and force
+    error against the precision leg's FP64 direct sum at the same targets;
+    base_ms is the plain FP32 walk's time (pair_groups = 0)."""
+    import numpy as np
+    import torch
+
+    import paper_1412_0659_amd as bh
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(snap.pos).to(dev)
+    mass = torch.from_numpy(snap.mass).to(dev)
+    rows = []
+    for cap in caps:
+        tree = bh.Tree(snap.n, pair_groups=cap)
+        tree.build(pos, mass)
+        ms, acc, pot, st = _timed_force(tree, theta, eps, reps)
+        tree.close()
+        ea = _rel(acc[idx], ref[0])
+        rows.append({"pair_groups": cap, "walk_ms": ms, "speedup_vs_groups": base_ms / ms,
+                     "target_sets": st["ngroups"],
+                     "pp_per_particle": st["n_pp"] / snap.n, "pc_per_particle": st["n_pc"] / snap.n,
+                     "err_acc_median": float(np.median(ea)),
+                     "err_acc_p99": float(np.percentile(ea, 99))})
+        log(f"[bench] paired target sets <= {cap}: walk {ms:.2f} ms ({base_ms / ms:.3f}x)")
+    return {"note": "sibling groups of together <= pair_groups particles walked as one target "
+                    "set (bh_params.pair_groups); the default walk (pair_groups = 0) is the "
+                    "headline", "rows": rows}
+
+
 def precision_sweep(name="disk_halo_4m", thetas=(0.3, 0.4, 0.6), log=print):
     """The precision form's table: FP32 and FP16 far-field walks at several
     opening angles, errors against one FP64 direct sum."""
@@ -813,6 +843,8 @@ def main(argv=None):
                          "reference kernel for scaling the HBM byte counters)")
     ap.add_argument("--no-c4", action="store_true",
                     help="skip the 4M precision sweep over theta 0.3 / 0.4 / 0.6")
+    ap.add_argument("--no-pairs", action="store_true",
+                    help="skip the paired-target-set walks (pair_groups 32, 48, 64)")
     ap.add_argument("--no-param-sweep", action="store_true",
                     help="skip the walk cost curve over theta, nleaf and ncrit")
     ap.add_argument("--profile-kernels", type=str, default=None, metavar="META_JSON",
@@ -983,8 +1015,11 @@ def main(argv=None):
     anchors = []
     if not args.no_precision:
         out["precision"] = precision(snap, theta, eps, log=log)
-        out["precision"].pop("_ref")
+        ref = out["precision"].pop("_ref")
         a = out["precision"].pop("_anchor")
+        if not args.no_pairs:
+            out["paired_target_sets"] = paired_sets(snap, theta, eps, ref, a["idx"],
+                                                    out["precision"]["fp32"]["walk_ms"], log=log)
         a["name"] = f"{args.workload} theta {theta}"
         anchors.append(a)
         f16 = out["precision"]["fp16_far"]

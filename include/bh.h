@@ -77,7 +77,15 @@ typedef struct bh_params {
                          (the paper's, Sec. III.B.1).  Every octree cell is one key
                          range under both, so the cells are the same; only their
                          order and the particle order inside them differ. */
-    int32_t reserved[2];
+    int32_t pair_groups; /* 0: off (the target groups above).  2..64: two
+                         consecutive groups 2k, 2k + 1 whose cells are siblings
+                         and that hold at most pair_groups particles together
+                         are walked as one target set, against the box of their
+                         union (Sec. III.A walks a group of targets at a time;
+                         the paper does not fix how targets are grouped).  Fewer
+                         walks, more interactions per target: the forces are the
+                         same method's, with more particle-particle terms. */
+    int32_t reserved;
 } bh_params;
 
 typedef struct bh_ctx bh_ctx;

@@ -47,7 +47,7 @@ class bh_params(ctypes.Structure):
     _fields_ = [("nleaf", ctypes.c_int32), ("ncrit", ctypes.c_int32),
                 ("far_fp16", ctypes.c_int32), ("pos_fp64", ctypes.c_int32),
                 ("adjoint", ctypes.c_int32), ("curve", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("pair_groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class bh_cic_grid(ctypes.Structure):
@@ -167,9 +167,10 @@ CURVES = {"morton": 0, "ph": 1}
 
 
 def bh_create(n_max: int, nleaf: int = 16, ncrit: int = 64, far_fp16: bool = False,
-              pos_fp64: bool = False, adjoint: bool = False, curve: str = "morton"):
+              pos_fp64: bool = False, adjoint: bool = False, curve: str = "morton",
+              pair_groups: int = 0):
     p = bh_params(nleaf, ncrit, int(bool(far_fp16)), int(bool(pos_fp64)), int(bool(adjoint)),
-                  CURVES[curve])
+                  CURVES[curve], int(pair_groups))
     out = _vp()
     rc = load().bh_create(ctypes.byref(out), int(n_max), ctypes.byref(p))
     _check(None, rc)
@@ -420,8 +421,10 @@ class Tree:
     """Owns one library context; methods call the C entry points."""
 
     def __init__(self, n_max: int, nleaf: int = 16, ncrit: int = 64, far_fp16: bool = False,
-                 pos_fp64: bool = False, adjoint: bool = False, curve: str = "morton"):
-        self.ctx = bh_create(n_max, nleaf, ncrit, far_fp16, pos_fp64, adjoint, curve)
+                 pos_fp64: bool = False, adjoint: bool = False, curve: str = "morton",
+                 pair_groups: int = 0):
+        self.ctx = bh_create(n_max, nleaf, ncrit, far_fp16, pos_fp64, adjoint, curve,
+                             pair_groups)
         self.n = 0
         self.pos_fp64 = bool(pos_fp64)
 

@@ -362,7 +362,8 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
     if (p) prm = *p;
     if (n_max <= 0 || prm.nleaf < 1 || prm.nleaf > 64 || prm.ncrit < 1 || prm.ncrit > 64 ||
         prm.far_fp16 < 0 || prm.far_fp16 > 1 || prm.pos_fp64 < 0 || prm.pos_fp64 > 1 ||
-        prm.adjoint < 0 || prm.adjoint > 1 || prm.curve < 0 || prm.curve > 1)
+        prm.adjoint < 0 || prm.adjoint > 1 || prm.curve < 0 || prm.curve > 1 ||
+        prm.pair_groups < 0 || prm.pair_groups == 1 || prm.pair_groups > 64)
         return BH_EINVAL;
     // cells: <= n leaves + 21 levels x n / (nleaf + 1) internal cells; the walk
     // packs a cell index into 29 bits
@@ -412,6 +413,7 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
         const char *g = std::getenv("BH_BUILD_GRID_LEVELS");
         c->forced_grid_levels = g && g[0] ? std::atoi(g) : -1;
     }
+    c->pair_groups = (uint32_t)prm.pair_groups;
     ok = ok && dalloc(&c->acc, n, err) && dalloc(&c->xyzm, n, err) &&
          dalloc(&c->spill, (size_t)c->walk_grid * kStackMax, err) && dalloc(&c->box, 8, err) &&
          dalloc(&c->box_part, 6 * 1024, err) && dalloc(&c->status, 4, err) &&

@@ -175,6 +175,7 @@ struct bh_ctx {
     int walk_grid = 0;
     bool walk_small_stack = false;  // test hook: 128-entry LDS stack window
     int forced_grid_levels = -1;    // test hook: levels split by the grid kernels
+    uint32_t pair_groups = 0;       // sibling groups of together <= this many walk as one (0: off)
 
     // events: build start, after sort, after octree+groups, after moments,
     // walk start, walk end, step start, step end, adjoint walk start, end

@@ -343,7 +343,8 @@ void launch_build(bh_ctx *ctx, uint32_t n, hipStream_t st, int grid_levels) {
 // keys) is cut into chunks of ncrit.  Group numbers follow key order: flag
 // each group's first particle, scan the flags.
 
-__global__ __launch_bounds__(256) void k_group_flags(Cells c, uint32_t ncrit, uint32_t *flag) {
+__global__ __launch_bounds__(256) void k_group_flags(Cells c, uint32_t ncrit, uint32_t *flag,
+                                                     uint32_t *gpar) {
     uint32_t nc = c.ls[kLevels];
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nc; i += gridDim.x * 256) {
         uint32_t cnt = c.count[i];
@@ -351,7 +352,10 @@ __global__ __launch_bounds__(256) void k_group_flags(Cells c, uint32_t ncrit, ui
         bool top = i == 0 || c.count[c.parent[i]] > ncrit;
         if (small && top) {
             uint32_t b = c.begin[i];
-            for (uint32_t s = 0; s < cnt; s += ncrit) flag[b + s] = 1u;
+            for (uint32_t s = 0; s < cnt; s += ncrit) {
+                flag[b + s] = 1u;
+                if (gpar) gpar[b + s] = i == 0 ? kNone : c.parent[i];
+            }
         }
     }
 }
@@ -369,15 +373,43 @@ __global__ __launch_bounds__(256) void k_group_fill(const uint32_t *__restrict__
     }
 }
 
+// Paired target sets (bh_params.pair_groups = cap, off by default): groups
+// 2k and 2k + 1 that are siblings (group cells with one parent; gpar holds
+// it at each group's first particle) and hold at most cap particles together
+// become one target set, walked once against the box of their union, by
+// clearing the start flag of group 2k + 1.
+__global__ __launch_bounds__(256) void k_pair_flags(const uint32_t *__restrict__ gbeg,
+                                                    const uint32_t *__restrict__ ngroups,
+                                                    const uint32_t *__restrict__ gpar,
+                                                    uint32_t cap, uint32_t *flag) {
+    const uint32_t ng = *ngroups;
+    for (uint32_t j = 2 * (blockIdx.x * 256 + threadIdx.x) + 1; j < ng;
+         j += 2 * gridDim.x * 256) {
+        const uint32_t a = gbeg[j - 1], b = gbeg[j];
+        if (gbeg[j + 1] - a <= cap && gpar[a] == gpar[b] && gpar[a] != kNone) flag[b] = 0u;
+    }
+}
+
 void launch_groups(bh_ctx *ctx, uint32_t n, hipStream_t st) {
     Groups &g = ctx->groups;
     launch_fill_u32(g.flag, 0u, n, st);
+    // paired target sets: each group's parent cell is kept in npp until the walk
+    uint32_t *gpar = ctx->pair_groups ? g.npp : nullptr;
     hipLaunchKernelGGL(k_group_flags, dim3(kGrid), dim3(256), 0, st, ctx->cells,
-                       (uint32_t)ctx->p.ncrit, g.flag);
+                       (uint32_t)ctx->p.ncrit, g.flag, gpar);
     launch_exclusive_scan(g.flag, g.scan, n, ctx->sort.scan_part, st);
     hipLaunchKernelGGL(k_group_fill, dim3(cdiv(n, 256)), dim3(256), 0, st,
                        (const uint32_t *)g.flag, (const uint32_t *)g.scan, n, g.begin,
                        g.count_dev);
+    if (ctx->pair_groups) {
+        hipLaunchKernelGGL(k_pair_flags, dim3(kGrid), dim3(256), 0, st,
+                           (const uint32_t *)g.begin, (const uint32_t *)g.count_dev,
+                           (const uint32_t *)gpar, ctx->pair_groups, g.flag);
+        launch_exclusive_scan(g.flag, g.scan, n, ctx->sort.scan_part, st);
+        hipLaunchKernelGGL(k_group_fill, dim3(cdiv(n, 256)), dim3(256), 0, st,
+                           (const uint32_t *)g.flag, (const uint32_t *)g.scan, n, g.begin,
+                           g.count_dev);
+    }
 }
 
 }  // namespace bh

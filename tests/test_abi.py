@@ -39,6 +39,9 @@ def test_host_argument_checks():
     for nleaf, ncrit, f16 in [(0, 64, 0), (16, 0, 0), (16, 65, 0), (65, 64, 0), (16, 64, 2)]:
         p = bh.binding.bh_params(nleaf, ncrit, f16, 0)
         assert L.bh_create(ctypes.byref(out), 100, ctypes.byref(p)) == bh.binding.BH_EINVAL
+    for pg in (-1, 1, 65):
+        p = bh.binding.bh_params(16, 64, 0, 0, 0, 0, pg)
+        assert L.bh_create(ctypes.byref(out), 100, ctypes.byref(p)) == bh.binding.BH_EINVAL
     # too many particles for the 29-bit cell index of the walk stack
     assert L.bh_create(ctypes.byref(out), 1 << 28, None) == bh.binding.BH_EINVAL
     assert L.bh_destroy(None) == bh.binding.BH_EINVAL

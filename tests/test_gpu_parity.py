@@ -250,3 +250,45 @@ def test_every_group_size(oracle):
     assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
     assert np.median(ep) <= MED_TOL and np.percentile(ep, 99) <= P99_TOL
     t.close()
+
+
+def _paired_groups(oracle, ot, cap):
+    """The oracle tree with groups 2k and 2k + 1 merged when their cells are
+    siblings and they hold at most cap particles together (boxes of the
+    merged target sets recomputed)."""
+    import dataclasses
+    j = np.arange(1, ot.ngroups, 2)
+    par = ot.cells["parent"][ot.gcell]
+    keep = np.ones(ot.ngroups, bool)
+    sib = (par[j - 1] == par[j]) & (ot.gcell[j - 1] != 0)
+    keep[j[(ot.gcnt[j - 1] + ot.gcnt[j] <= cap) & sib]] = False
+    gbeg = np.ascontiguousarray(ot.gbeg[keep])
+    gcnt = np.diff(np.append(gbeg, ot.n)).astype(np.int64)
+    gc, gh = oracle.group_boxes(gbeg, gcnt, ot.x, ot.y, ot.z)
+    return dataclasses.replace(ot, gbeg=gbeg, gcnt=gcnt, gcell=ot.gcell[keep], gc=gc, gh=gh)
+
+
+@pytest.mark.parametrize("cap", [2, 32, 48, 64])
+def test_paired_groups(oracle, cap):
+    """Paired target sets (pair_groups = cap): sibling groups of together at
+    most cap particles walked as one target set with the box of their union.
+    Groups, counts and forces against the oracle walked over the same merged
+    target sets."""
+    from paper_1412_0659_amd import Tree
+    d = ics.disk_halo(20000, 80000, 12)
+    print(f"paired groups cap={cap}", flush=True)
+    t = Tree(len(d.mass), pair_groups=cap)
+    t.build(to_dev(d.pos), to_dev(d.mass))
+    ot = _paired_groups(oracle, oracle.build_tree(d.pos, d.mass), cap)
+    assert np.array_equal(t.export("group_begin").astype(np.int64), ot.gbeg)
+    assert np.array_equal(t.export("group_count").astype(np.int64), ot.gcnt)
+    assert ot.gcnt.max() <= 64
+    assert ot.ngroups < oracle.build_tree(d.pos, d.mass).ngroups or cap < 3
+    acc, pot = gpu_force(t, 0.4, 1e-3)
+    oacc, opot, onpp, onpc = oracle.walk(ot, 0.4, 1e-3)
+    assert np.array_equal(t.export("group_npp").astype(np.int64), onpp)
+    assert np.array_equal(t.export("group_npc").astype(np.int64), onpc)
+    ea, ep = rel_err(acc, oacc), rel_err(pot, opot)
+    assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
+    assert np.median(ep) <= MED_TOL and np.percentile(ep, 99) <= P99_TOL
+    t.close()
