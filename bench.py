@@ -458,9 +458,10 @@ def param_sweep(name="disk_halo_4m", thetas=(0.3, 0.4, 0.5, 0.6, 0.8),
     return {"workload": name, "n": snap.n, "eps": w["eps"], "rows": rows}
 
 
-def adjoint(name="disk_halo_1m_adjoint", log=print):
+def adjoint(name="disk_halo_1m_adjoint", log=print, pair_groups=0):
     """The differentiation workload: K KDK steps forward with checkpoints,
-    surface-density loss, reverse sweep; forward and backward wall time."""
+    surface-density loss, reverse sweep; forward and backward wall time
+    (pair_groups: the context's paired target sets, 0 = groups)."""
     import numpy as np
     import torch
 
@@ -472,7 +473,7 @@ def adjoint(name="disk_halo_1m_adjoint", log=print):
     tgt_ic = ics.perturbed(s, w["target_seed"])
     dev = torch.device("cuda:0")
     sel = torch.from_numpy(s.is_disk.astype(np.uint8)).to(dev)
-    tree = bh.Tree(s.n, adjoint=True, pos_fp64=True)
+    tree = bh.Tree(s.n, adjoint=True, pos_fp64=True, pair_groups=pair_groups)
     # target: the density the perturbed initial conditions reach after K steps
     with torch.no_grad():
         xt, _ = leapfrog(torch.from_numpy(tgt_ic.pos).to(dev), torch.from_numpy(tgt_ic.vel).to(dev),
@@ -646,6 +647,46 @@ def write_counters(out_path, meta_path, dbs, command):
     with open(out_path, "w") as f:
         json.dump(doc, f, indent=1)
     return doc
+
+
+def counters_text(json_path):
+    """The committed counter JSON as a text table: per kernel, the counters
+    per dispatch, the counted flops (FLOPS counters x 64 lanes) per
+    interaction and against the paper's convention, the rate at the profiled
+    time and the VALU issue rate per SIMD."""
+    with open(json_path) as f:
+        d = json.load(f)
+    lines = ["# rocprofv3 --pmc VALU instruction mix and flop counters of the walk kernels (13M disk "
+             "+ halo,",
+             "# theta 0.4, eps 0.002: FP32 walk and FP16 far-field walk) and of the force VJP (1M "
+             "differentiation",
+             "# workload's initial state); means per dispatch over the profiled dispatches, summed "
+             "over the chip.",
+             f"# walk source sha256/16 {d['walk_source_sha256_16']}, VJP source sha256/16 "
+             f"{d['vjp_source_sha256_16']}",
+             f"# command: {d['command']}; python3 bench.py --counters-text "
+             f"profiles/{os.path.basename(json_path)}",
+             "#   (from the repository root; OUT: any output directory; the JSON beside this file "
+             "holds the same numbers)", "#"]
+    simds = 256 * 4
+    for name, c in d["kernels"].items():
+        lines.append(f"{name}:")
+        for k in sorted(k for k in c if k.startswith("SQ_")) + ["mean_ms"]:
+            lines.append(f"   {k:34s} {c[k]:.4e}")
+        hw, _ = counter_flops(c)
+        if "interactions" in c:
+            inter, paper = c["interactions"], None
+        else:
+            inter, paper = c["n_pp"] + c["n_pc"], paper_flops(c["n_pp"], c["n_pc"])
+        tf = hw / (c["mean_ms"] * 1e-3) / 1e12
+        extra = f"; / paper convention {hw / paper:.3f}" if paper else ""
+        lines.append(f"   counted flops (FLOPS counters x 64) {hw:.4e}; per interaction "
+                     f"{hw / inter:.1f}{extra}; at the profiled time {tf:.1f} TFLOP/s = "
+                     f"{tf / PEAK_FP32_TFLOPS:.3f} of {PEAK_FP32_TFLOPS}")
+        rate = c["SQ_INSTS_VALU"] / (c["mean_ms"] * 1e-3 * 2.4e9 * simds)
+        lines.append(f"   VALU wave-instructions per SIMD per cycle (2.4 GHz, {simds} SIMDs) "
+                     f"{rate:.3f}")
+    return "\n".join(lines) + "\n"
 
 
 def trace_summary(paths, top=30):
@@ -844,7 +885,8 @@ def main(argv=None):
     ap.add_argument("--no-c4", action="store_true",
                     help="skip the 4M precision sweep over theta 0.3 / 0.4 / 0.6")
     ap.add_argument("--no-pairs", action="store_true",
-                    help="skip the paired-target-set walks (pair_groups 32, 48, 64)")
+                    help="skip the paired-target-set runs (walks at pair_groups 32, 48, 64; "
+                         "the adjoint at 48)")
     ap.add_argument("--no-param-sweep", action="store_true",
                     help="skip the walk cost curve over theta, nleaf and ncrit")
     ap.add_argument("--profile-kernels", type=str, default=None, metavar="META_JSON",
@@ -860,6 +902,8 @@ def main(argv=None):
     ap.add_argument("--write-traffic", nargs=5, default=None, metavar="ARG",
                     help="OUT_JSON FETCH_DB WRITE_DB COPY_FETCH_DB COPY_WRITE_DB: write the "
                          "committed walk traffic summary")
+    ap.add_argument("--counters-text", nargs=2, default=None, metavar=("JSON", "OUT"),
+                    help="render the committed counter JSON as the text table")
     ap.add_argument("--write-build-traffic", nargs=4, default=None,
                     metavar=("OUT", "FETCH_DB", "WRITE_DB", "BENCH_JSON"),
                     help="write the build-phase HBM bytes summary from two --pmc runs")
@@ -875,6 +919,12 @@ def main(argv=None):
         out, dbs = args.write_traffic[0], args.write_traffic[1:]
         print(json.dumps(write_traffic(out, *dbs, os.environ.get("BH_PROFILE_COMMAND", "")),
                          indent=1))
+        return 0
+    if args.counters_text:
+        text = counters_text(args.counters_text[0])
+        with open(args.counters_text[1], "w") as f:
+            f.write(text)
+        print(text)
         return 0
     if args.write_build_traffic:
         out, f_db, w_db, bj = args.write_build_traffic
@@ -1037,6 +1087,13 @@ def main(argv=None):
     if not args.no_adjoint:
         out["adjoint"] = adjoint(log=log)
         ad = out["adjoint"]
+        if not args.no_pairs:
+            p48 = adjoint(log=log, pair_groups=48)
+            ad["paired_target_sets_48"] = {
+                k: p48[k] for k in ("forward_s", "backward_s", "backward_over_forward",
+                                    "walk_vjp_kernel_ms", "walk_vjp_interactions")}
+            ad["paired_target_sets_48"]["every_step_backward_over_forward"] = \
+                p48["every_step_snapshots"]["backward_over_forward"]
         c = (counters or {}).get("k_walk_vjp<false>")
         rep = None
         if c and c.get("interactions"):

@@ -63,3 +63,19 @@ def rel_err(a, ref):
     if a.ndim == 1:
         return np.abs(a - ref) / np.abs(ref)
     return np.sqrt(((a - ref) ** 2).sum(1)) / np.sqrt((ref ** 2).sum(1))
+
+
+def paired_groups(oracle, ot, cap):
+    """The oracle tree with groups 2k and 2k + 1 merged when their cells are
+    siblings and they hold at most cap particles together (boxes of the
+    merged target sets recomputed)."""
+    import dataclasses
+    j = np.arange(1, ot.ngroups, 2)
+    par = ot.cells["parent"][ot.gcell]
+    keep = np.ones(ot.ngroups, bool)
+    sib = (par[j - 1] == par[j]) & (ot.gcell[j - 1] != 0)
+    keep[j[(ot.gcnt[j - 1] + ot.gcnt[j] <= cap) & sib]] = False
+    gbeg = np.ascontiguousarray(ot.gbeg[keep])
+    gcnt = np.diff(np.append(gbeg, ot.n)).astype(np.int64)
+    gc, gh = oracle.group_boxes(gbeg, gcnt, ot.x, ot.y, ot.z)
+    return dataclasses.replace(ot, gbeg=gbeg, gcnt=gcnt, gcell=ot.gcell[keep], gc=gc, gh=gh)

@@ -20,7 +20,7 @@ master for these runs.
 import numpy as np
 import pytest
 
-from gpu_util import device, rel_err, to_dev
+from gpu_util import device, paired_groups, rel_err, to_dev
 from workloads import ics
 
 pytestmark = pytest.mark.gpu
@@ -67,6 +67,31 @@ def test_force_vjp_matches_oracle(oracle, case):
     assert np.median(em) <= 1e-5 and np.percentile(em, 99) <= 1e-4
     dd = rng.normal(size=(n, 3))
     assert abs((gp1 * dd).sum() - (gx_ref * dd).sum()) <= 1e-5 * np.abs(gx_ref * dd).sum()
+
+
+def test_force_vjp_paired_target_sets(oracle):
+    """The force VJP on a context with paired target sets (pair_groups = 48)
+    against the oracle's adjoint over the same merged sets."""
+    n, theta, eps = 20000, 0.4, 0.005
+    s = ics.disk_halo_scaled(n, 51)
+    u = np.random.default_rng(53).normal(size=(n, 3)).astype(np.float32)
+    t = _dev_tree(n, pair_groups=48)
+    t.build(to_dev(s.pos), to_dev(s.mass))
+    gp, gm = _zeros(n, 3), _zeros(n)
+    t.force_vjp(theta, eps, to_dev(u), 1.0, gp, gm)
+    t.sync()
+    ng = t.stats()["ngroups"]
+    gp, gm = gp.cpu().numpy().astype(np.float64), gm.cpu().numpy().astype(np.float64)
+    t.close()
+    ot = paired_groups(oracle, oracle.build_tree(s.pos, s.mass), 48)
+    assert ng == ot.ngroups
+    gx_ref, gm_ref = oracle.frozen_force_vjp(oracle.record_decisions(ot, theta), s.pos, s.mass,
+                                             eps, u)
+    ex, em = rel_err(gp, gx_ref), rel_err(gm, gm_ref)
+    print(f"paired force vjp: pos med {np.median(ex):.2e} p99 {np.percentile(ex, 99):.2e}; "
+          f"mass med {np.median(em):.2e} p99 {np.percentile(em, 99):.2e}")
+    assert np.median(ex) <= 1e-5 and np.percentile(ex, 99) <= 1e-4
+    assert np.median(em) <= 1e-5 and np.percentile(em, 99) <= 1e-4
 
 
 GRID = (0.2, 4.0, 16, 32)

@@ -7,7 +7,7 @@ within 1e-5 median / 1e-4 99th-percentile relative error.
 import numpy as np
 import pytest
 
-from gpu_util import assert_tree_equal, gpu_force, gpu_tree, rel_err, to_dev
+from gpu_util import assert_tree_equal, gpu_force, gpu_tree, paired_groups, rel_err, to_dev
 from workloads import ics
 
 pytestmark = pytest.mark.gpu
@@ -252,22 +252,6 @@ def test_every_group_size(oracle):
     t.close()
 
 
-def _paired_groups(oracle, ot, cap):
-    """The oracle tree with groups 2k and 2k + 1 merged when their cells are
-    siblings and they hold at most cap particles together (boxes of the
-    merged target sets recomputed)."""
-    import dataclasses
-    j = np.arange(1, ot.ngroups, 2)
-    par = ot.cells["parent"][ot.gcell]
-    keep = np.ones(ot.ngroups, bool)
-    sib = (par[j - 1] == par[j]) & (ot.gcell[j - 1] != 0)
-    keep[j[(ot.gcnt[j - 1] + ot.gcnt[j] <= cap) & sib]] = False
-    gbeg = np.ascontiguousarray(ot.gbeg[keep])
-    gcnt = np.diff(np.append(gbeg, ot.n)).astype(np.int64)
-    gc, gh = oracle.group_boxes(gbeg, gcnt, ot.x, ot.y, ot.z)
-    return dataclasses.replace(ot, gbeg=gbeg, gcnt=gcnt, gcell=ot.gcell[keep], gc=gc, gh=gh)
-
-
 @pytest.mark.parametrize("cap", [2, 32, 48, 64])
 def test_paired_groups(oracle, cap):
     """Paired target sets (pair_groups = cap): sibling groups of together at
@@ -279,7 +263,7 @@ def test_paired_groups(oracle, cap):
     print(f"paired groups cap={cap}", flush=True)
     t = Tree(len(d.mass), pair_groups=cap)
     t.build(to_dev(d.pos), to_dev(d.mass))
-    ot = _paired_groups(oracle, oracle.build_tree(d.pos, d.mass), cap)
+    ot = paired_groups(oracle, oracle.build_tree(d.pos, d.mass), cap)
     assert np.array_equal(t.export("group_begin").astype(np.int64), ot.gbeg)
     assert np.array_equal(t.export("group_count").astype(np.int64), ot.gcnt)
     assert ot.gcnt.max() <= 64
