@@ -276,3 +276,27 @@ def test_paired_groups(oracle, cap):
     assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
     assert np.median(ep) <= MED_TOL and np.percentile(ep, 99) <= P99_TOL
     t.close()
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 65, 130, 1000])
+def test_paired_groups_small_and_ragged(oracle, n):
+    """Paired target sets at tiny and ragged sizes (a lone root group, groups
+    without a sibling, odd group counts): groups and counts bit-exact, forces
+    within the bar, against the oracle over the same merged sets."""
+    from paper_1412_0659_amd import Tree
+    rng = np.random.default_rng(300 + n)
+    pos = rng.normal(size=(n, 3)).astype(np.float32)
+    m = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    print(f"paired groups small n={n}", flush=True)
+    t = Tree(n, pair_groups=64)
+    t.build(to_dev(pos), to_dev(m))
+    ot = paired_groups(oracle, oracle.build_tree(pos, m), 64)
+    assert np.array_equal(t.export("group_begin").astype(np.int64), ot.gbeg)
+    acc, pot = gpu_force(t, 0.5, 1e-2)
+    oacc, opot, onpp, onpc = oracle.walk(ot, 0.5, 1e-2)
+    assert np.array_equal(t.export("group_npp").astype(np.int64), onpp)
+    assert np.array_equal(t.export("group_npc").astype(np.int64), onpc)
+    if n > 1:
+        ea = rel_err(acc, oacc)
+        assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
+    t.close()
