@@ -893,7 +893,8 @@ def main(argv=None):
                     help="only run the dispatches the committed VALU counters describe "
                          "(run under rocprofv3 --pmc); write their interaction counts here")
     ap.add_argument("--pmc-summary", nargs="+", default=None, metavar="DB",
-                    help="only print the per-kernel mean counters of rocprofv3 databases")
+                    help="only print the per-kernel mean counters of rocprofv3 databases "
+                         "(dispatches at least half as long as the kernel's longest)")
     ap.add_argument("--write-counters", nargs="+", default=None, metavar="ARG",
                     help="OUT_JSON META_JSON DB...: write the committed counter summary")
     ap.add_argument("--trace-summary", nargs="+", default=None, metavar="DB",
@@ -913,7 +914,7 @@ def main(argv=None):
         print(trace_summary(args.trace_summary))
         return 0
     if args.pmc_summary:
-        print(json.dumps(pmc_summary(args.pmc_summary), indent=1))
+        print(json.dumps(pmc_summary(args.pmc_summary, min_frac=0.5), indent=1))
         return 0
     if args.write_traffic:
         out, dbs = args.write_traffic[0], args.write_traffic[1:]
