@@ -324,6 +324,35 @@ typedef enum bh_array {
 int bh_export(bh_ctx *ctx, int array, void *dst, int64_t cap_bytes, int64_t *nbytes,
               hipStream_t s);
 
+/* The sorted keys of the last build (Sec. III.B.1) and its permutation
+ * (sorted slot -> caller index), copied to host memory: keys [n] u64 and
+ * perm [n] u32, n = the built particle count (bh_stats_get); either may be
+ * NULL.  Synchronises s.  Errors: BH_EINVAL (null ctx), BH_ESTATE (nothing
+ * built). */
+int bh_export_keys(bh_ctx *ctx, uint64_t *keys, uint32_t *perm, hipStream_t s);
+
+/* Device views of the last built tree (Sec. I.A cells, Eq. (1) moments, the
+ * walk's target groups), for callers that read the tree in place.  Every
+ * pointer is device memory owned by the context, valid until the next build
+ * or bh_destroy; nothing is copied. */
+typedef struct bh_tree_view {
+    int64_t n;                  /* particles */
+    int64_t ncells;             /* cells, breadth first (level, then key) */
+    int64_t ngroups;            /* target groups (or paired target sets) */
+    const uint32_t *level_start;/* [23] first cell of every level 0..21, then ncells */
+    const uint64_t *prefix;     /* [ncells] key >> 3 (21 - level) */
+    const uint32_t *level, *begin, *count, *child0, *nchild, *parent; /* [ncells] */
+    const double *M;            /* [ncells] FP64 mass */
+    const double *S;            /* [ncells][3] FP64 first moment (centre of mass = S / M) */
+    const double *Q;            /* [ncells][6] FP64 second moment about the centre of mass:
+                                   xx, yy, zz, xy, xz, yz */
+    const uint32_t *group_begin;/* [ngroups + 1] first sorted particle of every group, then n */
+} bh_tree_view;
+
+/* Fill *out with the views above (host struct).  Synchronises s to read the
+ * counts.  Errors: BH_EINVAL (null ctx or out), BH_ESTATE (nothing built). */
+int bh_export_tree(bh_ctx *ctx, bh_tree_view *out, hipStream_t s);
+
 /* ---- Several spatial domains on one device (Sec. III.B) -------------------
  *
  * The paper splits the particles into one domain per GPU along the

@@ -64,8 +64,18 @@ class bh_stats(ctypes.Structure):
                 ("ms_walk_vjp", ctypes.c_double)]
 
 
+class bh_tree_view(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("ncells", ctypes.c_int64), ("ngroups", ctypes.c_int64),
+                ("level_start", ctypes.c_void_p), ("prefix", ctypes.c_void_p),
+                ("level", ctypes.c_void_p), ("begin", ctypes.c_void_p), ("count", ctypes.c_void_p),
+                ("child0", ctypes.c_void_p), ("nchild", ctypes.c_void_p),
+                ("parent", ctypes.c_void_p), ("M", ctypes.c_void_p), ("S", ctypes.c_void_p),
+                ("Q", ctypes.c_void_p), ("group_begin", ctypes.c_void_p)]
+
+
 SYMBOLS = ["bh_create", "bh_destroy", "tree_build", "bh_set_state", "tree_force",
            "leapfrog_step", "bh_get_state", "bh_sync", "bh_stats_get", "bh_export",
+           "bh_export_keys", "bh_export_tree",
            "bh_strerror", "bh_last_error", "tree_force_vjp", "leapfrog_vjp_drift",
            "bh_state_bytes", "bh_save_state", "bh_load_state", "bh_cic_density",
            "bh_cic_density_vjp", "tree_direct", "bh_diagnostics", "bh_set_box",
@@ -101,6 +111,8 @@ def load():
         "bh_sync": ([_vp, _vp], c_int),
         "bh_stats_get": ([_vp, ctypes.POINTER(bh_stats), _vp], c_int),
         "bh_export": ([_vp, c_int, _vp, i64, ctypes.POINTER(i64), _vp], c_int),
+        "bh_export_keys": ([_vp, _vp, _vp, _vp], c_int),
+        "bh_export_tree": ([_vp, ctypes.POINTER(bh_tree_view), _vp], c_int),
         "bh_strerror": ([c_int], ctypes.c_char_p),
         "bh_last_error": ([_vp], ctypes.c_char_p),
         "tree_force_vjp": ([_vp, f32, f32, _vp, f32, _vp, _vp, _vp], c_int),
@@ -227,6 +239,22 @@ def bh_export(ctx, name: str, count: int, stream=None) -> np.ndarray:
     k = nb.value // np.dtype(dt).itemsize
     out = out[:k]
     return out.reshape(-1, width) if width > 1 else out
+
+
+def bh_export_keys(ctx, n: int, stream=None):
+    """Sorted keys (u64) and permutation (u32) of the last build, host copies."""
+    keys = np.empty(n, np.uint64)
+    perm = np.empty(n, np.uint32)
+    _check(ctx, load().bh_export_keys(ctx, keys.ctypes.data_as(_vp), perm.ctypes.data_as(_vp),
+                                      _stream(stream)))
+    return keys, perm
+
+
+def bh_export_tree(ctx, stream=None) -> bh_tree_view:
+    """Device views of the last built tree (pointers owned by the context)."""
+    v = bh_tree_view()
+    _check(ctx, load().bh_export_tree(ctx, ctypes.byref(v), _stream(stream)))
+    return v
 
 
 def _u8ptr(t):

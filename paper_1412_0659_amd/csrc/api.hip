@@ -658,6 +658,38 @@ int bh_export(bh_ctx *c, int array, void *dst, int64_t cap_bytes, int64_t *nbyte
     return check_status(c);
 }
 
+int bh_export_keys(bh_ctx *c, uint64_t *keys, uint32_t *perm, hipStream_t s) {
+    if (!c) return BH_EINVAL;
+    if (!c->built) return fail(c, BH_ESTATE, "nothing built");
+    BH_HIP(c, hipStreamSynchronize(s));
+    const size_t n = (size_t)c->n;
+    if (keys && n) BH_HIP(c, hipMemcpy(keys, c->sort.key[0], 8 * n, hipMemcpyDeviceToHost));
+    if (perm && n) BH_HIP(c, hipMemcpy(perm, c->st[c->cur].cid, 4 * n, hipMemcpyDeviceToHost));
+    return check_status(c);
+}
+
+int bh_export_tree(bh_ctx *c, bh_tree_view *out, hipStream_t s) {
+    if (!c || !out) return BH_EINVAL;
+    if (!c->built) return fail(c, BH_ESTATE, "nothing built");
+    BH_HIP(c, hipStreamSynchronize(s));
+    uint32_t ls[kLsSize], ng = 0;
+    BH_HIP(c, hipMemcpy(ls, c->cells.ls, sizeof(ls), hipMemcpyDeviceToHost));
+    BH_HIP(c, hipMemcpy(&ng, c->groups.count_dev, sizeof(ng), hipMemcpyDeviceToHost));
+    const Cells &q = c->cells;
+    bh_tree_view v{};
+    v.n = c->n;
+    v.ncells = ls[kLevels];
+    v.ngroups = ng;
+    v.level_start = q.ls;
+    v.prefix = q.prefix;
+    v.level = q.level; v.begin = q.begin; v.count = q.count;
+    v.child0 = q.child0; v.nchild = q.nchild; v.parent = q.parent;
+    v.M = q.M; v.S = q.S; v.Q = q.Q;
+    v.group_begin = c->groups.begin;
+    *out = v;
+    return check_status(c);
+}
+
 int tree_force_vjp(bh_ctx *c, float theta, float eps, const float *u, float coef,
                    float *g_pos, float *g_mass, hipStream_t s) {
     if (!c) return BH_EINVAL;

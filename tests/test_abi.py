@@ -51,6 +51,8 @@ def test_host_argument_checks():
     assert L.bh_sync(None, None) == bh.binding.BH_EINVAL
     assert L.tree_direct(None, None, 1, 0.01, None, None, None) == bh.binding.BH_EINVAL
     assert L.bh_diagnostics(None, None, None) == bh.binding.BH_EINVAL
+    assert L.bh_export_keys(None, None, None, None) == bh.binding.BH_EINVAL
+    assert L.bh_export_tree(None, None, None) == bh.binding.BH_EINVAL
     assert L.bh_strerror(bh.binding.BH_ESTATE) == b"call out of order"
     assert L.bh_last_error(None) == b""
 

@@ -300,3 +300,41 @@ def test_paired_groups_small_and_ragged(oracle, n):
         ea = rel_err(acc, oacc)
         assert np.median(ea) <= MED_TOL and np.percentile(ea, 99) <= P99_TOL
     t.close()
+
+
+def _d2h(ptr, count, dtype):
+    """Copy `count` elements at a device address to host through the HIP
+    runtime already in the process (opened by its soname, so torch's copy)."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    out = np.empty(count, dtype)
+    assert hip.hipMemcpy(ctypes.c_void_p(out.ctypes.data), ctypes.c_void_p(ptr),
+                         ctypes.c_size_t(out.nbytes), 2) == 0  # device to host
+    return out
+
+
+def test_export_keys_and_tree_views(oracle):
+    """bh_export_keys and the device views of bh_export_tree against the
+    oracle tree (keys, permutation, cells, FP64 moments, groups)."""
+    from paper_1412_0659_amd import binding as B
+    d = ics.disk_halo(20000, 80000, 12)
+    t = gpu_tree(d.pos, d.mass)
+    ot = oracle.build_tree(d.pos, d.mass)
+    keys, perm = B.bh_export_keys(t.ctx, len(d.mass))
+    assert np.array_equal(keys, ot.skeys) and np.array_equal(perm.astype(np.int64), ot.perm)
+    v = B.bh_export_tree(t.ctx)
+    oc = ot.cells
+    assert (v.n, v.ncells, v.ngroups) == (len(d.mass), oc["ncell"], ot.ngroups)
+    nc = oc["ncell"]
+    assert np.array_equal(_d2h(v.level_start, 23, np.uint32).astype(np.int64), oc["level_start"])
+    assert np.array_equal(_d2h(v.prefix, nc, np.uint64), oc["prefix"])
+    for k in ("level", "begin", "count", "nchild"):
+        assert np.array_equal(_d2h(getattr(v, k), nc, np.uint32).astype(np.int64),
+                              oc[k].astype(np.int64)), k
+    assert np.array_equal(_d2h(v.M, nc, np.float64), ot.mom["M"])
+    S = _d2h(v.S, 3 * nc, np.float64).reshape(nc, 3)
+    assert np.array_equal(S / _d2h(v.M, nc, np.float64)[:, None], ot.mom["com"])
+    assert np.array_equal(_d2h(v.Q, 6 * nc, np.float64).reshape(nc, 6), ot.mom["Q"])
+    gb = _d2h(v.group_begin, ot.ngroups + 1, np.uint32).astype(np.int64)
+    assert np.array_equal(gb[:-1], ot.gbeg) and gb[-1] == len(d.mass)
+    t.close()
