@@ -146,13 +146,17 @@ void launch_keys(bh_ctx *c, const State &s, uint32_t n, hipStream_t st) {
 
 // ---- LSD radix sort, 8 bits per pass -------------------------------------
 //
-// A tile is 2048 keys handled by 256 threads (4 waves x 8 rounds x 64
+// A tile is 8192 keys handled by 1024 threads (16 waves x 8 rounds x 64
 // lanes); wave w owns the contiguous keys [512 w, 512 w + 512) of the tile,
 // in rounds of 64 consecutive keys, so (wave, round, lane) order is input
 // order and the ranking below is stable.  Pass structure: per-tile digit
-// counts -> one exclusive scan over (digit, tile) -> stable scatter.
+// counts -> one exclusive scan over (digit, tile) -> stable scatter.  A tile
+// of 8192 keys gives digit runs of 32 keys on average, so the scatter writes
+// mostly whole cache lines (the tile and its reorder buffer, 112 KB of LDS,
+// fit one workgroup of gfx950).
 
-constexpr int kSortThreads = 256;
+constexpr int kSortThreads = 1024;
+constexpr int kSortWaves = kSortThreads / 64;
 constexpr int kSortRounds = 8;
 constexpr int kSortTile = kSortThreads * kSortRounds;
 
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(const uint64_t *__r
                                                              uint32_t ntiles,
                                                              uint32_t *__restrict__ counts) {
     __shared__ uint32_t hist[256];
-    hist[threadIdx.x] = 0;
+    if (threadIdx.x < 256) hist[threadIdx.x] = 0;
     __syncthreads();
     uint32_t w = threadIdx.x >> 6, lane = lane_id();
     uint64_t base = (uint64_t)blockIdx.x * kSortTile + w * 512 + lane;
@@ -173,16 +177,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(const uint64_t *__r
         if (i < n) atomicAdd(&hist[(uint32_t)(key[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    counts[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
+    if (threadIdx.x < 256) counts[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint64_t *__restrict__ key_in, const uint32_t *__restrict__ idx_in, uint32_t n,
     uint32_t shift, uint32_t ntiles, const uint32_t *__restrict__ offsets,
     uint64_t *__restrict__ key_out, uint32_t *__restrict__ idx_out) {
-    __shared__ uint32_t cnt[4][256];
+    __shared__ uint32_t cnt[kSortWaves][256];
     uint32_t w = threadIdx.x >> 6, lane = lane_id();
-    for (int k = 0; k < 4; ++k) cnt[k][threadIdx.x] = 0;
+    for (int k = 0; k < kSortWaves * 256; k += kSortThreads)
+        (&cnt[0][0])[k + threadIdx.x] = 0;
     __syncthreads();
     uint64_t base = (uint64_t)blockIdx.x * kSortTile + w * 512 + lane;
     uint64_t kk[kSortRounds];
@@ -223,21 +228,28 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     __shared__ uint32_t sidx[kSortTile];
     __shared__ uint32_t wsum[4];
     __shared__ int32_t delta[256];
-    {
+    uint32_t tot = 0, lo = 0;
+    if (threadIdx.x < 256) {  // waves 0..3: one digit per thread
         const uint32_t d = threadIdx.x;
-        const uint32_t c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d], c3 = cnt[3][d];
-        const uint32_t tot = c0 + c1 + c2 + c3;
+#pragma unroll
+        for (int k = 0; k < kSortWaves; ++k) tot += cnt[k][d];
         const uint32_t inc = wave_incl_scan(tot, lane);
         if (lane == 63) wsum[w] = inc;
-        __syncthreads();
-        uint32_t lo = inc - tot;
+        lo = inc - tot;
+    }
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        const uint32_t d = threadIdx.x;
         for (uint32_t k = 0; k < w; ++k) lo += wsum[k];
         const uint32_t g = offsets[(uint64_t)d * ntiles + blockIdx.x];
         delta[d] = (int32_t)(g - lo);
-        cnt[0][d] = lo;
-        cnt[1][d] = lo + c0;
-        cnt[2][d] = lo + c0 + c1;
-        cnt[3][d] = lo + c0 + c1 + c2;
+        uint32_t run = lo;
+#pragma unroll
+        for (int k = 0; k < kSortWaves; ++k) {
+            const uint32_t c = cnt[k][d];
+            cnt[k][d] = run;
+            run += c;
+        }
     }
     __syncthreads();
 #pragma unroll
