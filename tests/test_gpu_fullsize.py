@@ -64,3 +64,66 @@ def test_precision_form_full_size(oracle):
         print(f"  theta {theta}: FP32 tree vs direct med {row[0][0]:.2e} p99 {row[0][1]:.2e}; "
               f"FP16 far med {row[1][0]:.2e} p99 {row[1][1]:.2e}", flush=True)
         assert row[1][0] <= 1e-3
+
+
+def _group_subset(oracle, d, sel):
+    """The decisions of the groups `sel` only (their lists, on the same tree
+    topology): the frozen-decision VJP of a cotangent that is zero outside
+    those groups' targets is the same computed over them alone."""
+    import dataclasses
+    t = d.tree
+    npc = d.pc_off[sel + 1] - d.pc_off[sel]
+    nlf = d.lf_off[sel + 1] - d.lf_off[sel]
+    pc = np.concatenate([d.pc[d.pc_off[g]:d.pc_off[g + 1]] for g in sel])
+    lf = np.concatenate([d.lf[d.lf_off[g]:d.lf_off[g + 1]] for g in sel])
+    sub = dataclasses.replace(t, gbeg=np.ascontiguousarray(t.gbeg[sel]),
+                              gcnt=np.ascontiguousarray(t.gcnt[sel]),
+                              gcell=np.ascontiguousarray(t.gcell[sel]),
+                              gc=np.ascontiguousarray(t.gc[sel]), gh=np.ascontiguousarray(t.gh[sel]))
+    return oracle.Decisions(sub, np.concatenate([[0], np.cumsum(npc)]).astype(np.int64),
+                            np.ascontiguousarray(pc, np.int64),
+                            np.concatenate([[0], np.cumsum(nlf)]).astype(np.int64),
+                            np.ascontiguousarray(lf, np.int64))
+
+
+def test_force_vjp_full_size_sampled_targets(oracle):
+    """The force VJP at the differentiation workload's full size (1M disk +
+    halo, theta 0.4), in the launch configuration the benchmark times, for
+    a cotangent that is nonzero only on the targets of 1500 seeded groups:
+    every particle's gradient (targets, and sources through particle-particle
+    terms and the cell moments) against the oracle's frozen-decision
+    adjoint over those groups."""
+    import torch
+    from paper_1412_0659_amd import Tree
+    w = ics.DIFF_WORKLOADS["disk_halo_1m_adjoint"]
+    s = ics.disk_halo_scaled(w["n"], w["seed"])
+    n = s.n
+    print(f"case force vjp 1m n={n} theta={w['theta']} eps={w['eps']}", flush=True)
+    ot = oracle.build_tree(s.pos, s.mass)
+    d = oracle.record_decisions(ot, w["theta"])
+    rng = np.random.default_rng(78)
+    sel = np.sort(rng.choice(ot.ngroups, size=1500, replace=False))
+    u = np.zeros((n, 3), np.float32)
+    tgt = np.concatenate([ot.perm[ot.gbeg[g]:ot.gbeg[g] + ot.gcnt[g]] for g in sel])
+    u[tgt] = rng.normal(size=(len(tgt), 3)).astype(np.float32)
+    gx_ref, gm_ref = oracle.frozen_force_vjp(_group_subset(oracle, d, sel), s.pos, s.mass,
+                                             w["eps"], u)
+    t = Tree(n, adjoint=True)
+    t.build(torch.from_numpy(s.pos).cuda(), torch.from_numpy(s.mass).cuda())
+    gp = torch.zeros(n, 3, device="cuda")
+    gm = torch.zeros(n, device="cuda")
+    t.force_vjp(w["theta"], w["eps"], torch.from_numpy(u).cuda(), 1.0, gp, gm)
+    t.sync()
+    gp, gm = gp.cpu().numpy().astype(np.float64), gm.cpu().numpy().astype(np.float64)
+    t.close()
+    # every particle the sampled groups reach, with a floor at 1e-3 of the
+    # largest gradient for the ones they barely reach
+    for name, a, b in (("g_pos", gp, gx_ref), ("g_mass", gm, gm_ref)):
+        a2, b2 = a.reshape(n, -1), b.reshape(n, -1)
+        nb = np.linalg.norm(b2, axis=1)
+        hit = nb > 0
+        e = np.linalg.norm(a2 - b2, axis=1)[hit] / np.maximum(nb[hit], 1e-3 * nb.max())
+        print(f"  {name}: {hit.sum()} particles reached, median {np.median(e):.2e} "
+              f"p99 {np.percentile(e, 99):.2e}", flush=True)
+        assert np.median(e) <= 1e-5 and np.percentile(e, 99) <= 1e-4, name
+        assert not a2[~hit].any(), name
