@@ -127,3 +127,8 @@ def test_force_vjp_full_size_sampled_targets(oracle):
               f"p99 {np.percentile(e, 99):.2e}", flush=True)
         assert np.median(e) <= 1e-5 and np.percentile(e, 99) <= 1e-4, name
         assert not a2[~hit].any(), name
+        # the sampled targets themselves, each against its own gradient's norm
+        et = np.linalg.norm(a2[tgt] - b2[tgt], axis=1) / np.linalg.norm(b2[tgt], axis=1)
+        print(f"  {name} at the {len(tgt)} sampled targets: median {np.median(et):.2e} "
+              f"p99 {np.percentile(et, 99):.2e}", flush=True)
+        assert np.median(et) <= 1e-5 and np.percentile(et, 99) <= 1e-4, name
