@@ -180,3 +180,34 @@ def test_moments_bottom_up_equal_direct_sums(oracle):
     assert np.array_equal(mo["lf"], (t.side * np.float32(2.0) ** -lev.astype(np.float32)).astype(np.float32))
     # the centre of mass of a cell lies inside the cell: delta <= sqrt(3)/2 l
     assert np.all(mo["deltaf"] <= np.float32(0.8661) * mo["lf"] * (1 + 1e-5))
+
+
+def test_paired_target_sets_helper(oracle):
+    """The merged target sets the paired-group parity tests build from the
+    oracle's groups: they partition the particles in key order, each holds
+    at most the cap or is one original group, a merged set is exactly two
+    consecutive sibling groups 2k, 2k + 1, and every such pair within the cap
+    is merged."""
+    import numpy as np
+    from gpu_util import paired_groups
+    from workloads import ics
+    d = ics.disk_halo(4000, 16000, 12)
+    ot = oracle.build_tree(d.pos, d.mass)
+    par = ot.cells["parent"][ot.gcell]
+    for cap in (2, 32, 48, 64):
+        pt = paired_groups(oracle, ot, cap)
+        assert pt.gbeg[0] == 0 and np.all(np.diff(pt.gbeg) > 0)
+        assert np.array_equal(np.append(pt.gbeg[1:], ot.n) - pt.gbeg, pt.gcnt)
+        starts = set(ot.gbeg.tolist())
+        assert set(pt.gbeg.tolist()) <= starts
+        dropped = sorted(starts - set(pt.gbeg.tolist()))
+        idx = {b: k for k, b in enumerate(ot.gbeg.tolist())}
+        for b in dropped:  # the start of group 2k + 1, merged into 2k
+            j = idx[b]
+            assert j % 2 == 1 and par[j] == par[j - 1] and ot.gcell[j - 1] != 0
+            assert ot.gcnt[j - 1] + ot.gcnt[j] <= cap
+        for j in range(1, ot.ngroups, 2):  # every qualifying pair is merged
+            if par[j] == par[j - 1] and ot.gcell[j - 1] != 0 and ot.gcnt[j - 1] + ot.gcnt[j] <= cap:
+                assert int(ot.gbeg[j]) in dropped
+        gc, gh = oracle.group_boxes(pt.gbeg, pt.gcnt, ot.x, ot.y, ot.z)
+        assert np.array_equal(gc, pt.gc) and np.array_equal(gh, pt.gh)
