@@ -30,8 +30,8 @@
  *     or throws across the ABI.  bh_last_error() describes the last failure.
  *   - Conditions found on the device (a non-finite position or a
  *     non-positive mass at build time) are latched in a device status word
- *     and reported by the next synchronising call (bh_sync, bh_stats,
- *     bh_export, bh_get_state).
+ *     and reported by the next synchronising call (bh_sync, bh_stats_get,
+ *     bh_export, bh_export_keys, bh_export_tree, bh_get_state).
  */
 #ifndef BH_H
 #define BH_H
