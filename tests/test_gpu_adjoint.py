@@ -446,7 +446,9 @@ def test_vjp_segment_matches_per_step_sweep():
         e = np.linalg.norm(a - b) / np.linalg.norm(b)
         print(f"autograd vs per-step sweep {name}: rel L2 {e:.2e}")
         assert e <= 1e-6, (name, e)
-    # argument checks
+    # argument checks (the tree is held in a name: a temporary would be
+    # destroyed, and its context freed, before the call)
+    t2 = _dev_tree(n, pos_fp64=True)
     with pytest.raises(B.BhError):
-        B.leapfrog_vjp_segment(_dev_tree(n, pos_fp64=True).ctx, snaps[0], n, 0, 0, dt, theta,
-                               eps, gx, gv)
+        B.leapfrog_vjp_segment(t2.ctx, snaps[0], n, 0, 0, dt, theta, eps, gx, gv)
+    t2.close()
