@@ -252,7 +252,7 @@ void weight_cuts(std::vector<std::pair<uint64_t, int64_t>> smp, int32_t pieces,
 namespace {
 
 constexpr int64_t kStaticMaxN = BH_STATIC_MAX_N;
-constexpr int kStaticWalkGrid = 2048;          // persistent walk waves (stack spill per wave)
+constexpr int kStaticWalkGrid = 1024;          // persistent walk waves (stack spill per wave)
 constexpr size_t kStaticBytes = size_t(64) << 20;
 constexpr int kMaxDevices = 64;
 

@@ -21,7 +21,7 @@ constexpr int kBuildGrid = 2048;        // grid of the octree level kernels: 8 w
 constexpr int kTableLevel = 7;          // the build looks up the child bounds of levels < 7
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kNone = 0xffffffffu;
-constexpr int kStackMax = 1408;         // walk stack bound: 21 levels x 64 ranges + root
+constexpr int kStackMax = 2689;         // walk stack bound: 21 levels x 128 ranges + root
 constexpr int kDiagN = 9;               // diagnostics: M, KE, PE, p xyz, L xyz
 constexpr int kDiagBlocks = 1024;       // blocks of the diagnostics reduction
 
@@ -173,7 +173,7 @@ struct bh_ctx {
     float box_lo[3] = {0.f, 0.f, 0.f}, box_side = 1.f;
     float acc_theta = 0.f, acc_eps = 0.f;
     int walk_grid = 0;
-    bool walk_small_stack = false;  // test hook: 128-entry LDS stack window
+    bool walk_small_stack = false;  // test hook: at most 192 resident stack entries
     int forced_grid_levels = -1;    // test hook: levels split by the grid kernels
     uint32_t pair_groups = 0;       // sibling groups of together <= this many walk as one (0: off)
 

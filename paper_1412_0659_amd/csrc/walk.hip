@@ -25,7 +25,7 @@ struct WalkArgs {
     float4 *acc, *gbox;
     uint32_t *npp, *npc, *status;
     float eps2;
-    uint32_t ring;  // ring entries in use: kRing, or 128 to exercise the spill path
+    uint32_t ring;  // resident stack entries allowed: kRing, or 192 to exercise the spill path
     uint32_t remote;  // 1: the walked tree is another domain's (no self pair)
     uint32_t accum;   // 1: add to acc, npp, npc instead of overwriting them
 };
@@ -467,7 +467,7 @@ void launch_walk_view(bh_ctx *c, const SrcView &v, float eps, bool remote, bool 
     a.acc = c->acc; a.gbox = c->groups.box;
     a.npp = c->groups.npp; a.npc = c->groups.npc; a.status = c->status;
     a.eps2 = eps * eps;
-    a.ring = c->walk_small_stack ? 128u : (uint32_t)kRing;
+    a.ring = c->walk_small_stack ? 192u : (uint32_t)kRing;
     a.remote = remote ? 1u : 0u;
     a.accum = accum ? 1u : 0u;
     hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(64), 0, st, c->work);

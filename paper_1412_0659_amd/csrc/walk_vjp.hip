@@ -451,7 +451,7 @@ void launch_walk_vjp(bh_ctx *c, float eps, const float *u, float coef, float *g_
     a.P0 = c->cells.P0; a.P1 = c->cells.P1; a.P2 = c->cells.P2;
     a.gbeg = c->groups.begin; a.ngroups = c->groups.count_dev;
     a.work = c->work; a.spill = c->spill; a.status = c->status;
-    a.ring = c->walk_small_stack ? 128u : (uint32_t)kRing;
+    a.ring = c->walk_small_stack ? 192u : (uint32_t)kRing;
     a.lcell = c->lcell; a.gsrc = c->gsrc;
     a.lstride = lstride; a.gstride = gstride;
     a.cap = cap; a.nmax = nmax;

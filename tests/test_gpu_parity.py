@@ -161,6 +161,42 @@ def test_coincident_points(oracle):
     t.close()
 
 
+def test_large_coincident_leaf(oracle):
+    """A level-21 leaf of 70 000 coincident particles: a traversal pass whose
+    opened leaves hold more than 2^16 particles (the particle-particle list
+    is filled across many flushes from one pass)."""
+    rng = np.random.default_rng(31)
+    nc = 70_000
+    pos = np.concatenate([np.full((nc, 3), 0.3), rng.uniform(0, 1, (2000, 3))]).astype(np.float32)
+    m = np.full(pos.shape[0], 1.0 / pos.shape[0], np.float32)
+    t = gpu_tree(pos, m)
+    ot = oracle.build_tree(pos, m)
+    assert_tree_equal(t, ot)
+    assert ot.cells["count"][ot.cells["nchild"] == 0].max() == nc
+    acc, pot = gpu_force(t, 0.5, 0.01)
+    # groups of the coincident leaf (first, middle, last) and every other group
+    cgroups = np.flatnonzero(np.isin(ot.gbeg, ot.perm.argsort()[:nc]))
+    rest = np.setdiff1d(np.arange(ot.ngroups), cgroups)
+    csel = cgroups[[0, len(cgroups) // 2, -1]]
+    sel = np.sort(np.concatenate([csel, rest]))
+    oacc, opot, onpp, onpc = oracle.walk(ot, 0.5, 0.01, groups=sel)
+    npp = t.export("group_npp").astype(np.int64)
+    assert np.array_equal(npp[sel], onpp[sel])
+    assert np.array_equal(t.export("group_npc").astype(np.int64)[sel], onpc[sel])
+    assert npp[cgroups[0]] >= nc
+    tgt = np.concatenate([ot.perm[ot.gbeg[g]:ot.gbeg[g] + ot.gcnt[g]] for g in sel])
+    nterm = np.concatenate([np.full(ot.gcnt[g], onpp[g] + onpc[g]) for g in sel])
+    ep = rel_err(pot[tgt], opot[tgt])
+    # a potential summed from ~70 000 equal FP32 terms: within the first-order
+    # bound of recursive summation, (number of terms) x 2^-24 relative (all
+    # terms of one sign); the other targets as everywhere else
+    big = nterm >= 10_000
+    assert big.sum() == ot.gcnt[csel].sum() and np.all(ep[big] <= nterm[big] * 2.0**-24)
+    assert np.percentile(ep[~big], 99) <= P99_TOL
+    assert np.max(np.abs(acc[tgt] - oacc[tgt])) <= 1e-4 * np.max(np.abs(oacc[tgt]))
+    t.close()
+
+
 @pytest.mark.parametrize("nleaf,ncrit", [(1, 1), (8, 32), (16, 64), (64, 16)])
 def test_tree_parameters(oracle, nleaf, ncrit):
     s = ics.disk_halo(2000, 8000, 14)
