@@ -60,7 +60,7 @@ void free_all(bh_ctx *c) {
     f(q.P2); f(q.size);
     Groups &g = c->groups;
     f(g.flag); f(g.scan); f(g.begin); f(g.count_dev); f(g.box); f(g.npp); f(g.npc);
-    f(c->lcell); f(c->gsrc); f(c->usort); f(c->leafof); f(c->cic); f(c->inv); f(c->diag);
+    f(c->lcell); f(c->gsrc); f(c->lhot); f(c->usort); f(c->leafof); f(c->cic); f(c->inv); f(c->diag);
     Boundary &b = c->bnd;
     f(b.flag); f(b.scan); f(b.ids); f(b.box); f(b.cmin); f(b.cmax); f(b.lvl); f(b.part);
     Let &t = c->let;
@@ -434,6 +434,7 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
          dalloc(&c->diag, (size_t)(kDiagBlocks + 1) * kDiagN, err);
     if (ok && prm.adjoint)
         ok = dalloc(&c->lcell, 8 * 10 * nc, err) && dalloc(&c->gsrc, 8 * 4 * n, err) &&
+             dalloc(&c->lhot, (size_t)kHotCopies * kHotCopy, err) &&
              dalloc(&c->usort, n, err) && dalloc(&c->leafof, n, err);
     for (auto &e : c->ev)
         if (ok && hipEventCreate(&e) != hipSuccess) ok = false;

@@ -22,6 +22,14 @@ constexpr int kTableLevel = 7;          // the build looks up the child bounds o
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr int kStackMax = 2689;         // walk stack bound: 21 levels x 128 ranges + root
+// Adjoint: the cells of the top levels (the first kHotCells in level order) are hit by far
+// more groups than the rest, so their accumulators come in kHotCopies copies (4 per XCD).
+// Field and copy strides (in doubles) are one 128-byte line more than a power-of-two
+// multiple, so that the copies and fields of a cell fall on different L2 channels.
+constexpr uint32_t kHotCells = 65536;
+constexpr uint32_t kHotCopies = 32;
+constexpr uint64_t kHotField = kHotCells + 16;
+constexpr uint64_t kHotCopy = 10 * kHotField + 16;
 constexpr int kDiagN = 9;               // diagnostics: M, KE, PE, p xyz, L xyz
 constexpr int kDiagBlocks = 1024;       // blocks of the diagnostics reduction
 
@@ -143,10 +151,12 @@ struct bh_ctx {
     bh::Groups groups{};
 
     // adjoint buffers (contexts created with adjoint = 1)
-    // per-XCD copies (8): [8][cap_cells][10] dL/dM, dL/dcom xyz, dL/dQ xx yy zz xy xz yz;
-    // [8][n_max][4] dL/dx xyz, dL/dm of sorted particles
+    // per-XCD copies (8), field-major: [8][10][cap_cells] dL/dM, dL/dcom xyz, dL/dQ xx yy zz
+    // xy xz yz; [8][4][n_max] dL/dx xyz, dL/dm of sorted particles; the first kHotCells
+    // cells accumulate in kHotCopies copies of kHotCopy doubles (field stride kHotField) instead
     double *lcell = nullptr;
     double *gsrc = nullptr;
+    double *lhot = nullptr;
     float4 *usort = nullptr;   // [n] cotangent of the accelerations, sorted order
     uint32_t *leafof = nullptr;  // [n] leaf cell of each sorted particle
     double *cic = nullptr;       // [65536] accumulator of the surface-density grid

@@ -25,7 +25,10 @@
 // particles of one leaf, share a few cache lines; and they come in kXcd
 // copies, one per XCD: a wave adds into the copy of the XCD it runs on (read
 // from the hardware XCC id), so no cache line is updated from two XCDs.  The
-// copies are summed after the walk.
+// cells of the top levels are accepted by far more groups than deeper ones
+// (a few cache lines of them take a quarter of all the atomics), so the first
+// kHotCells cells get kHotCopies copies, kHotCopies / kXcd per XCD chosen by
+// the workgroup.  The copies are summed after the walk.
 #include "walk_common.h"
 
 namespace bh {
@@ -59,6 +62,9 @@ struct VjpArgs {
     // atomic instruction (neighbouring cells or particles) share cache lines
     double *lcell, *gsrc;
     uint64_t lstride, gstride, cap, nmax;
+    // kHotCopies copies of the first kHotCells cells' adjoints, copy k at
+    // lhot + k * kHotCopy, field q of cell c at + q * kHotField + c
+    double *lhot;
     float eps2;
 };
 
@@ -186,6 +192,8 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
     const uint32_t xcd = xcc_id();
     double *const lcx = a.lcell + xcd * a.lstride;
     double *const gsx = a.gsrc + xcd * a.gstride;
+    const uint32_t hk = xcd + kXcd * ((blockIdx.x / kXcd) % (kHotCopies / kXcd));
+    double *const lhx = a.lhot + hk * kHotCopy;
     const bool own = lane < gn;
     const uint32_t ti = gb + (own ? lane : 0u);
     const float4 me = a.xyzm[ti];
@@ -247,13 +255,15 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
                 }
             }
             if (valid) {
-                double *lc = lcx + c;
+                const bool hot = c < kHotCells;
+                double *lc = hot ? lhx + c : lcx + c;
+                const uint64_t fs = hot ? kHotField : a.cap;
                 add_l2(lc, (double)sM);
-                add_l2(lc + a.cap, (double)sw[0]);
-                add_l2(lc + 2 * a.cap, (double)sw[1]);
-                add_l2(lc + 3 * a.cap, (double)sw[2]);
+                add_l2(lc + fs, (double)sw[0]);
+                add_l2(lc + 2 * fs, (double)sw[1]);
+                add_l2(lc + 3 * fs, (double)sw[2]);
 #pragma unroll
-                for (int q = 0; q < 6; ++q) add_l2(lc + (4 + q) * a.cap, (double)sQ[q]);
+                for (int q = 0; q < 6; ++q) add_l2(lc + (4 + q) * fs, (double)sQ[q]);
             }
         }
         __syncthreads();
@@ -350,18 +360,18 @@ __global__ __launch_bounds__(256) void k_usort(const float *__restrict__ u,
     us[i] = make_float4(u[3 * p], u[3 * p + 1], u[3 * p + 2], 0.f);
 }
 
-// Zero the kXcd copies of F fields of cnt entries each (field q at q * fs;
-// cnt = the cell count of the current tree when ls is given).
+// Zero `copies` copies (copy k at k * stride) of F fields of cnt entries each
+// (field q at q * fs; cnt = the cell count of the current tree when ls is
+// given, at most `lim`).
 __global__ __launch_bounds__(256) void k_zero_xcd(double *p, uint64_t cnt, uint32_t F,
-                                                  uint64_t fs, uint64_t stride,
-                                                  const uint32_t *ls) {
-    if (ls) cnt = ls[kLevels];
+                                                  uint64_t fs, uint64_t stride, uint32_t copies,
+                                                  const uint32_t *ls, uint64_t lim) {
+    if (ls) cnt = ls[kLevels] < lim ? ls[kLevels] : lim;
     const uint64_t total = cnt * F;
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < total;
          i += (uint64_t)gridDim.x * 256) {
         const uint64_t q = i / cnt, e = i - q * cnt;
-#pragma unroll
-        for (uint32_t k = 0; k < kXcd; ++k) p[q * fs + e + k * stride] = 0.0;
+        for (uint32_t k = 0; k < copies; ++k) p[q * fs + e + k * stride] = 0.0;
     }
 }
 
@@ -379,6 +389,22 @@ __global__ __launch_bounds__(256) void k_fold_xcd(double *p, uint64_t cnt, uint3
 #pragma unroll
         for (uint32_t k = 1; k < kXcd; ++k) v += p[o + k * stride];
         p[o] = v;
+    }
+}
+
+// Add the kHotCopies copies of the first kHotCells cells' adjoints (copy k at
+// k * kHotCopy, field q at q * kHotField) to copy 0 of the cell accumulators
+// (field q of cell c at q * cap + c).
+__global__ __launch_bounds__(256) void k_fold_hot(const double *__restrict__ hot, double *lcell,
+                                                  uint64_t cap, const uint32_t *ls) {
+    const uint32_t nc = ls[kLevels] < kHotCells ? ls[kLevels] : kHotCells;
+    const uint32_t total = nc * 10u;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < total; i += gridDim.x * 256) {
+        const uint32_t q = i / nc, e = i - q * nc;
+        const double *h = hot + q * kHotField + e;
+        double v = 0.0;
+        for (uint32_t k = 0; k < kHotCopies; ++k) v += h[k * kHotCopy];
+        lcell[q * cap + e] += v;
     }
 }
 
@@ -439,9 +465,11 @@ void launch_walk_vjp(bh_ctx *c, float eps, const float *u, float coef, float *g_
     const uint64_t lstride = 10ull * cap, gstride = 4ull * nmax;
     const uint32_t *ls = c->cells.ls;
     hipLaunchKernelGGL(k_zero_xcd, dim3(2048), dim3(256), 0, st, c->lcell, (uint64_t)0, 10u, cap,
-                       lstride, ls);
+                       lstride, kXcd, ls, cap);
     hipLaunchKernelGGL(k_zero_xcd, dim3(grid), dim3(256), 0, st, c->gsrc, (uint64_t)n, 4u, nmax,
-                       gstride, (const uint32_t *)nullptr);
+                       gstride, kXcd, (const uint32_t *)nullptr, (uint64_t)n);
+    hipLaunchKernelGGL(k_zero_xcd, dim3(640), dim3(256), 0, st, c->lhot, (uint64_t)0, 10u,
+                       kHotField, kHotCopy, kHotCopies, ls, (uint64_t)kHotCells);
     hipLaunchKernelGGL(k_leafof, dim3(kGrid * 2), dim3(256), 0, st, c->cells, c->leafof);
     hipLaunchKernelGGL(k_usort, dim3(nb), dim3(256), 0, st, u,
                        (const uint32_t *)c->st[c->cur].cid, n, c->usort);
@@ -452,7 +480,7 @@ void launch_walk_vjp(bh_ctx *c, float eps, const float *u, float coef, float *g_
     a.gbeg = c->groups.begin; a.ngroups = c->groups.count_dev;
     a.work = c->work; a.spill = c->spill; a.status = c->status;
     a.ring = c->walk_small_stack ? 192u : (uint32_t)kRing;
-    a.lcell = c->lcell; a.gsrc = c->gsrc;
+    a.lcell = c->lcell; a.gsrc = c->gsrc; a.lhot = c->lhot;
     a.lstride = lstride; a.gstride = gstride;
     a.cap = cap; a.nmax = nmax;
     a.eps2 = eps * eps;
@@ -465,6 +493,8 @@ void launch_walk_vjp(bh_ctx *c, float eps, const float *u, float coef, float *g_
     record_event(c, 9, st);
     hipLaunchKernelGGL(k_fold_xcd, dim3(2048), dim3(256), 0, st, c->lcell, (uint64_t)0, 10u, cap,
                        lstride, ls);
+    hipLaunchKernelGGL(k_fold_hot, dim3(640), dim3(256), 0, st, (const double *)c->lhot, c->lcell,
+                       cap, ls);
     hipLaunchKernelGGL(k_fold_xcd, dim3(grid), dim3(256), 0, st, c->gsrc, (uint64_t)n, 4u, nmax,
                        gstride, (const uint32_t *)nullptr);
     hipLaunchKernelGGL(k_moments_vjp, dim3(nb), dim3(256), 0, st, c->cells,
