@@ -72,15 +72,20 @@ __device__ __forceinline__ float rsqv(float v) { return __builtin_amdgcn_rsqf(v)
 
 // Adjoint of one particle-cell term (records as in the force walk:
 // A = (com, M), B = -3 (Qxx, Qyy, Qzz, Qxy), C = (-3 Qxz, -3 Qyz, tr/2, -3 tr/2)).
-// w = J^T u; with kSrc also gM = dF/dM . u and gQ = dF/dQ . u for the six
-// stored entries of the (true) quadrupole.  With B = -3 Q:
+// Returns w = J^T u and adds the cell-side terms to running sums.  With
+// B = -3 Q, ctr = -3 tr / 2, ud = u.d:
 //   w = u [M r^-3 + ctr r^-5 - 5/2 dBd r^-7]
 //     + d [-3 M ud r^-5 - 5 ctr ud r^-7 - 5 uBd r^-7 + 35/2 dBd ud r^-9]
-//     + Bu r^-5 - 5 ud Bd r^-7          (ctr = -3 tr / 2, ud = u.d)
-template <bool kSrc>
+//     + Bu r^-5 - 5 ud Bd r^-7
+// dF/dM . u = ud r^-3 (added to sM).  dF/dQ . u for the six stored entries:
+// with v = r^-5 u - 5/2 ud r^-7 d,
+//   diagonal  -3 v_a d_a - 3/2 ud r^-5,   off-diagonal  -3 (v_a d_b + v_b d_a);
+// sQ collects the v-terms unscaled (diagonal v_a d_a, off-diagonal
+// v_a d_b + v_b d_a) and st the ud r^-5, so that the factors -3 and -3/2 are
+// applied once per sum (pc_adj_finish).
 __device__ __forceinline__ void pc_adj(const float4 &T, const float4 &U, const float4 &A,
                                        const float4 &B, const float4 &C, float eps2, float &wx,
-                                       float &wy, float &wz, float &gM, float *gQ) {
+                                       float &wy, float &wz, float &sM, float *sQ, float &st) {
     const float dx = A.x - T.x, dy = A.y - T.y, dz = A.z - T.z;
     const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, eps2)));
     const float ri = rsqv(r2);
@@ -95,23 +100,36 @@ __device__ __forceinline__ void pc_adj(const float4 &T, const float4 &U, const f
     const float q2 = fmaf(dx, bdx, fmaf(dy, bdy, dz * bdz)) * ri2;  // dBd / r^2
     const float uBd = fmaf(U.x, bdx, fmaf(U.y, bdy, U.z * bdz));
     const float M = A.w, ctr = C.w;
-    const float cu = fmaf(M, ri3, fmaf(ctr, ri5, -2.5f * q2 * ri5));
-    const float cd = fmaf(-3.f * M * ud, ri5,
-                          fmaf(-5.f * ctr * ud, ri7, fmaf(-5.f * uBd, ri7, 17.5f * q2 * ud * ri7)));
-    const float cb = -5.f * ud * ri7;
+    const float cu = fmaf(fmaf(-2.5f, q2, ctr), ri5, M * ri3);
+    const float udr7 = ud * ri7;
+    const float cd =
+        fmaf(ud, fmaf(-3.f * M, ri5, fmaf(17.5f, q2, -5.f * ctr) * ri7), -5.f * uBd * ri7);
+    const float cb = -5.f * udr7;
     wx = fmaf(cu, U.x, fmaf(cd, dx, fmaf(bux, ri5, cb * bdx)));
     wy = fmaf(cu, U.y, fmaf(cd, dy, fmaf(buy, ri5, cb * bdy)));
     wz = fmaf(cu, U.z, fmaf(cd, dz, fmaf(buz, ri5, cb * bdz)));
-    if (kSrc) {
-        gM = ud * ri3;
-        const float t5 = -1.5f * ud * ri5, t7 = 7.5f * ud * ri7, s5 = -3.f * ri5;
-        gQ[0] = fmaf(s5 * U.x, dx, fmaf(t7 * dx, dx, t5));
-        gQ[1] = fmaf(s5 * U.y, dy, fmaf(t7 * dy, dy, t5));
-        gQ[2] = fmaf(s5 * U.z, dz, fmaf(t7 * dz, dz, t5));
-        gQ[3] = fmaf(s5, fmaf(U.x, dy, U.y * dx), 2.f * t7 * dx * dy);
-        gQ[4] = fmaf(s5, fmaf(U.x, dz, U.z * dx), 2.f * t7 * dx * dz);
-        gQ[5] = fmaf(s5, fmaf(U.y, dz, U.z * dy), 2.f * t7 * dy * dz);
-    }
+    sM = fmaf(ud, ri3, sM);
+    st = fmaf(ud, ri5, st);
+    const float h = -2.5f * udr7;
+    const float vx = fmaf(h, dx, ri5 * U.x), vy = fmaf(h, dy, ri5 * U.y),
+                vz = fmaf(h, dz, ri5 * U.z);
+    sQ[0] = fmaf(vx, dx, sQ[0]);
+    sQ[1] = fmaf(vy, dy, sQ[1]);
+    sQ[2] = fmaf(vz, dz, sQ[2]);
+    sQ[3] = fmaf(vx, dy, fmaf(vy, dx, sQ[3]));
+    sQ[4] = fmaf(vx, dz, fmaf(vz, dx, sQ[4]));
+    sQ[5] = fmaf(vy, dz, fmaf(vz, dy, sQ[5]));
+}
+
+// dL/dQ of the six stored entries from the sums of pc_adj.
+__device__ __forceinline__ void pc_adj_finish(float *sQ, float st) {
+    const float t = -1.5f * st;
+    sQ[0] = fmaf(-3.f, sQ[0], t);
+    sQ[1] = fmaf(-3.f, sQ[1], t);
+    sQ[2] = fmaf(-3.f, sQ[2], t);
+    sQ[3] *= -3.f;
+    sQ[4] *= -3.f;
+    sQ[5] *= -3.f;
 }
 
 // Adjoint of one particle-particle term: F = m d r^-3, J = m (I r^-3 - 3 d d^T r^-5).
@@ -239,14 +257,12 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
                 r1 = a.P1[c];
                 r2 = a.P2[c];
             }
-            float sw[3] = {0.f, 0.f, 0.f}, sM = 0.f, sQ[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            float sw[3] = {0.f, 0.f, 0.f}, sM = 0.f, st = 0.f;
+            float sQ[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             for (uint32_t t = 0; t < gn; ++t) {
-                float wx, wy, wz, gM, gQ[6];
-                pc_adj<true>(L.tp[t], L.tu[t], r0, r1, r2, a.eps2, wx, wy, wz, gM, gQ);
+                float wx, wy, wz;
+                pc_adj(L.tp[t], L.tu[t], r0, r1, r2, a.eps2, wx, wy, wz, sM, sQ, st);
                 sw[0] += wx; sw[1] += wy; sw[2] += wz;
-                sM += gM;
-#pragma unroll
-                for (int q = 0; q < 6; ++q) sQ[q] += gQ[q];
                 const float tx = wave_total(wx), ty = wave_total(wy), tz = wave_total(wz);
                 if (lane == t) {
                     gtx -= tx;
@@ -254,6 +270,7 @@ __device__ void vjp_group(const VjpArgs &a, uint32_t g, uint32_t lane, VjpLds &L
                     gtz -= tz;
                 }
             }
+            pc_adj_finish(sQ, st);
             if (valid) {
                 const bool hot = c < kHotCells;
                 double *lc = hot ? lhx + c : lcx + c;
