@@ -280,6 +280,77 @@ def cpu_baseline(snap, theta, eps, budget_s=12.0):
     }
 
 
+def cpu_configs(anchors=None, walk_budget_s=3.0):
+    """The oracle on the other workloads, on this host: the 16k Plummer sphere
+    (full tree force at theta 0.3 / 0.5 / 0.7 and the full O(N^2) direct sum,
+    tree-vs-direct error per theta), the 1M disk + halo (tree build and a
+    seeded sample of its group walks), and the 4M direct sum at sampled
+    targets (taken from the error anchors when given)."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from workloads import ics
+    out = {}
+    w = ics.WORKLOADS["plummer_16k"]
+    s = ics.make("plummer_16k")
+    t0 = time.perf_counter()
+    tree = O.build_tree(s.pos, s.mass)
+    t_build = time.perf_counter() - t0
+    eps32 = float(np.float32(w["eps"]))
+    t0 = time.perf_counter()
+    da, dp = O.direct(s.pos, s.mass, eps32)
+    t_direct = time.perf_counter() - t0
+    per_theta = {}
+    for theta in (0.3, 0.5, 0.7):
+        t0 = time.perf_counter()
+        acc, pot, npp, npc = O.walk(tree, theta, w["eps"])
+        dt = time.perf_counter() - t0
+        inter = int(((npp + npc) * tree.gcnt).sum())
+        e = _rel(acc, da)
+        per_theta[str(theta)] = {"walk_s": dt, "interactions_per_s": inter / dt,
+                                 "err_acc_median": float(np.median(e)),
+                                 "err_acc_p99": float(np.percentile(e, 99))}
+    out["plummer_16k"] = {
+        "n": s.n, "eps": w["eps"], "tree_build_s": t_build, "tree": per_theta,
+        "direct_s": t_direct, "direct_pairs_per_s": float(s.n) * s.n / t_direct,
+        "note": "full FP64 oracle tree force per theta and full FP64 direct sum; errors of "
+                "the oracle tree against the oracle direct sum"}
+    w = ics.WORKLOADS["disk_halo_1m"]
+    s = ics.make("disk_halo_1m")
+    t0 = time.perf_counter()
+    tree = O.build_tree(s.pos, s.mass)
+    t_build = time.perf_counter() - t0
+    order = np.random.default_rng(4321).permutation(tree.ngroups)
+    done, inter, walk_s, k = 0, 0, 0.0, 64
+    while done < len(order) and walk_s < walk_budget_s:
+        sel = order[done:done + k]
+        t1 = time.perf_counter()
+        _, _, npp, npc = O.walk(tree, w["theta"], w["eps"], groups=sel)
+        walk_s += time.perf_counter() - t1
+        inter += int(((npp[sel] + npc[sel]) * tree.gcnt[sel]).sum())
+        done += len(sel)
+        k = min(4 * k, 4096)
+    targets = int(tree.gcnt[order[:done]].sum())
+    rate = inter / walk_s
+    out["disk_halo_1m"] = {
+        "n": s.n, "theta": w["theta"], "eps": w["eps"], "tree_build_s": t_build,
+        "sample": f"{done} random groups ({targets} targets), {walk_s:.1f} s of walk",
+        "interactions_per_s": rate,
+        "full_walk_s_estimated": inter / targets * s.n / rate}
+    for a in anchors or []:
+        if a["name"].startswith("disk_halo_4m"):
+            idx = a["idx"][:256]
+            t0 = time.perf_counter()
+            O.direct(a["pos"], a["mass"], np.float32(a["eps"]), targets=idx)
+            dt = time.perf_counter() - t0
+            n = len(a["mass"])
+            out["disk_halo_4m"] = {
+                "n": n, "direct_targets": int(len(idx)), "direct_s": dt,
+                "direct_pairs_per_s": float(n) * len(idx) / dt,
+                "direct_65536_targets_s_estimated": dt * 65536 / len(idx)}
+    return out
+
+
 def hbm_phases(n, ncells, ms_sort, ms_moments, pos_fp64=False, ms_build=None, depth=None):
     """Algorithmic HBM bytes of the tree-build phases and the rate they imply.
 
@@ -1136,6 +1207,8 @@ def main(argv=None):
         if anchors:
             log("[bench] oracle anchors of the force errors ...")
             out["cpu_baseline"]["oracle_anchors"] = oracle_anchors(anchors)
+        log("[bench] oracle on the other workloads ...")
+        out["cpu_baseline"]["configs"] = cpu_configs(anchors)
     out["ms_phase"] = {k: float(v) for k, v in out["ms_phase"].items()}
     print(json.dumps(out))
     return 0
