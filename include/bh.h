@@ -72,7 +72,8 @@ typedef struct bh_params {
                          from its FP32 rounding.  0: FP32 positions. */
     int32_t adjoint;  /* 1: allocate the buffers of tree_force_vjp: FP64 cell and
                          particle adjoints, one copy per XCD (8): 640 bytes per
-                         cell of capacity + 276 bytes per particle */
+                         cell of capacity + 276 bytes per particle, and 168 MB
+                         for 32 further copies of the first 65536 cells' */
     int32_t curve;    /* space-filling curve of the keys: 0 Morton, 1 Peano-Hilbert
                          (the paper's, Sec. III.B.1).  Every octree cell is one key
                          range under both, so the cells are the same; only their
@@ -281,7 +282,7 @@ int bh_stats_get(bh_ctx *ctx, bh_stats *out, hipStream_t s);
 
 /* Arrays that bh_export can copy out, with element type and count. */
 typedef enum bh_array {
-    BH_ARR_KEYS = 1,        /* u64 [n]      sorted Morton keys */
+    BH_ARR_KEYS = 1,        /* u64 [n]      sorted keys (Morton; Peano-Hilbert with curve = 1) */
     BH_ARR_PERM = 2,        /* u32 [n]      sorted slot -> caller index */
     BH_ARR_BOX = 3,         /* f32 [5]      lo x, y, z, side, scale */
     BH_ARR_LEVEL_START = 4, /* u32 [23]     first cell of each level; [22] = ncells */
