@@ -30,6 +30,7 @@ constexpr uint32_t kStage = 16;
 struct MomArgs {
     Cells c;
     const float *x, *y, *z, *m;
+    const float4 *xyzm;  // the same particles as (x, y, z, m) records, one load each
     const float *box;  // lo xyz, side
     int curve;
 };
@@ -48,8 +49,8 @@ __device__ __forceinline__ void leaf_sums(const MomArgs &a, uint32_t b, uint32_t
         float px[kStage], py[kStage], pz[kStage], pm[kStage];
 #pragma unroll
         for (uint32_t k = 0; k < kStage; ++k) {
-            const uint32_t j = k < cnt ? b + k : b;
-            px[k] = a.x[j]; py[k] = a.y[j]; pz[k] = a.z[j]; pm[k] = a.m[j];
+            const float4 p = a.xyzm[k < cnt ? b + k : b];
+            px[k] = p.x; py[k] = p.y; pz[k] = p.z; pm[k] = p.w;
         }
 #pragma unroll
         for (uint32_t k = 0; k < kStage; ++k) {
@@ -128,13 +129,15 @@ __device__ __forceinline__ void parent_sums(const Cells &c, uint32_t k0, uint32_
             const uint32_t j = k0 + k;
             const double mk = cm[k];
             const double d0 = cs0[k] / mk - c0, d1 = cs1[k] / mk - c1, d2 = cs2[k] / mk - c2;
-            const double *qk = c.Q + 6 * (size_t)j;
-            q0 = q0 + (qk[0] + (mk * d0) * d0);
-            q1 = q1 + (qk[1] + (mk * d1) * d1);
-            q2 = q2 + (qk[2] + (mk * d2) * d2);
-            q3 = q3 + (qk[3] + (mk * d0) * d1);
-            q4 = q4 + (qk[4] + (mk * d0) * d2);
-            q5 = q5 + (qk[5] + (mk * d1) * d2);
+            // the six entries as three 16-byte loads (Q is 16-byte aligned, 48 bytes a cell)
+            const double2 *qk = reinterpret_cast<const double2 *>(c.Q) + 3 * (size_t)j;
+            const double2 qa = qk[0], qb = qk[1], qc = qk[2];
+            q0 = q0 + (qa.x + (mk * d0) * d0);
+            q1 = q1 + (qa.y + (mk * d1) * d1);
+            q2 = q2 + (qb.x + (mk * d2) * d2);
+            q3 = q3 + (qb.y + (mk * d0) * d1);
+            q4 = q4 + (qc.x + (mk * d0) * d2);
+            q5 = q5 + (qc.y + (mk * d1) * d2);
         }
     }
     r = Mom{mm, s0, s1, s2, q0, q1, q2, q3, q4, q5};
@@ -173,8 +176,10 @@ __device__ __forceinline__ void cell_pass(const MomArgs &a, uint32_t i, uint32_t
     }
     c.M[i] = r.M;
     c.S[3 * i] = r.s0; c.S[3 * i + 1] = r.s1; c.S[3 * i + 2] = r.s2;
-    double *q = c.Q + 6 * (size_t)i;
-    q[0] = r.q0; q[1] = r.q1; q[2] = r.q2; q[3] = r.q3; q[4] = r.q4; q[5] = r.q5;
+    double2 *q = reinterpret_cast<double2 *>(c.Q) + 3 * (size_t)i;
+    q[0] = make_double2(r.q0, r.q1);
+    q[1] = make_double2(r.q2, r.q3);
+    q[2] = make_double2(r.q4, r.q5);
 
     // walk records: com (FP32), opening-radius terms, particle-cell record
     const double lo0 = a.box[0], lo1 = a.box[1], lo2 = a.box[2], side = a.box[3];
@@ -223,6 +228,7 @@ void launch_moments(bh_ctx *ctx, hipStream_t st, int grid_levels) {
     MomArgs a;
     a.c = ctx->cells;
     a.x = s.x; a.y = s.y; a.z = s.z; a.m = s.m;
+    a.xyzm = ctx->xyzm;
     a.box = ctx->box;
     a.curve = (int)ctx->p.curve;
     const int L = grid_levels < 0 ? 0 : (grid_levels > kLevels - 1 ? kLevels - 1 : grid_levels);
