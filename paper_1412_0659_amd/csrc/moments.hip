@@ -161,16 +161,19 @@ __device__ __forceinline__ void cell_coords(uint64_t prefix, uint32_t lev, uint3
 template <bool kStaged>
 __device__ __forceinline__ void cell_pass(const MomArgs &a, uint32_t i, uint32_t lev) {
     const Cells &c = a.c;
-    const uint32_t nch = c.nchild[i];
+    // the cell's topology in one round of loads (every field is defined for
+    // every cell; child0 is only used by parents, begin and count by leaves)
+    const uint32_t nch = c.nchild[i], b0 = c.begin[i], n0 = c.count[i], k0 = c.child0[i];
+    const uint64_t prefix = c.prefix[i];
     Mom r;
     double c0, c1, c2;
     uint32_t first, cnt;
     if (nch == 0) {
-        first = c.begin[i];
-        cnt = c.count[i];
+        first = b0;
+        cnt = n0;
         leaf_sums<kStaged>(a, first, cnt, r, c0, c1, c2);
     } else {
-        first = c.child0[i];
+        first = k0;
         cnt = nch;
         parent_sums(c, first, nch, r, c0, c1, c2);
     }
@@ -184,7 +187,7 @@ __device__ __forceinline__ void cell_pass(const MomArgs &a, uint32_t i, uint32_t
     // walk records: com (FP32), opening-radius terms, particle-cell record
     const double lo0 = a.box[0], lo1 = a.box[1], lo2 = a.box[2], side = a.box[3];
     uint32_t p[3];
-    cell_coords(c.prefix[i], lev, p);     // the digits, deinterleaved
+    cell_coords(prefix, lev, p);          // the digits, deinterleaved
     if (a.curve == 1) ph_decode(p, (int)lev);  // Peano-Hilbert prefix -> octant
     const double lc = side * (1.0 / (double)(1u << lev));
     const double e0 = c0 - (lo0 + ((double)p[0] + 0.5) * lc);
