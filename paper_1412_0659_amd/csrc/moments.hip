@@ -100,16 +100,24 @@ __device__ __forceinline__ void leaf_sums(const MomArgs &a, uint32_t b, uint32_t
     r = Mom{mm, s0, s1, s2, q0, q1, q2, q3, q4, q5};
 }
 
-// A parent reads the mass, first and second moments of its (at most eight)
-// children at once, then sums them in child order; a child's centre of mass
-// is its S / M, the same division that made it.
+// A parent reads the mass, first and second moments (and with kStaged the
+// quadrupoles) of its (at most eight) children at once, then sums them in
+// child order; a child's centre of mass is its S / M, the same division that
+// made it.
+template <bool kStaged>
 __device__ __forceinline__ void parent_sums(const Cells &c, uint32_t k0, uint32_t nch, Mom &r,
                                             double &c0, double &c1, double &c2) {
     double cm[8], cs0[8], cs1[8], cs2[8];
+    double2 cq[8][3];  // the six quadrupole entries as three 16-byte loads
+    const double2 *Q2 = reinterpret_cast<const double2 *>(c.Q);  // 16-byte aligned
 #pragma unroll
     for (uint32_t k = 0; k < 8; ++k) {
         const uint32_t j = k0 + (k < nch ? k : 0u);
         cm[k] = c.M[j]; cs0[k] = c.S[3 * j]; cs1[k] = c.S[3 * j + 1]; cs2[k] = c.S[3 * j + 2];
+        if (kStaged) {
+            cq[k][0] = Q2[3 * (size_t)j]; cq[k][1] = Q2[3 * (size_t)j + 1];
+            cq[k][2] = Q2[3 * (size_t)j + 2];
+        }
     }
     double mm = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
 #pragma unroll
@@ -126,12 +134,11 @@ __device__ __forceinline__ void parent_sums(const Cells &c, uint32_t k0, uint32_
 #pragma unroll
     for (uint32_t k = 0; k < 8; ++k) {
         if (k < nch) {
-            const uint32_t j = k0 + k;
             const double mk = cm[k];
             const double d0 = cs0[k] / mk - c0, d1 = cs1[k] / mk - c1, d2 = cs2[k] / mk - c2;
-            // the six entries as three 16-byte loads (Q is 16-byte aligned, 48 bytes a cell)
-            const double2 *qk = reinterpret_cast<const double2 *>(c.Q) + 3 * (size_t)j;
-            const double2 qa = qk[0], qb = qk[1], qc = qk[2];
+            const size_t j = k0 + k;
+            const double2 qa = kStaged ? cq[k][0] : Q2[3 * j], qb = kStaged ? cq[k][1] : Q2[3 * j + 1],
+                          qc = kStaged ? cq[k][2] : Q2[3 * j + 2];
             q0 = q0 + (qa.x + (mk * d0) * d0);
             q1 = q1 + (qa.y + (mk * d1) * d1);
             q2 = q2 + (qb.x + (mk * d2) * d2);
@@ -175,7 +182,7 @@ __device__ __forceinline__ void cell_pass(const MomArgs &a, uint32_t i, uint32_t
     } else {
         first = k0;
         cnt = nch;
-        parent_sums(c, first, nch, r, c0, c1, c2);
+        parent_sums<kStaged>(c, first, nch, r, c0, c1, c2);
     }
     c.M[i] = r.M;
     c.S[3 * i] = r.s0; c.S[3 * i + 1] = r.s1; c.S[3 * i + 2] = r.s2;
