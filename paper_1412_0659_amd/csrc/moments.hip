@@ -218,10 +218,10 @@ __global__ __launch_bounds__(256) void k_moments_level(MomArgs a, int l) {
         cell_pass<true>(a, i, (uint32_t)l);
 }
 
-// Levels 20 down to l1 in one workgroup (the deep end of the tree, few or no
+// Levels l0 down to l1 in one workgroup (the deep end of the tree, few or no
 // cells), the same per-cell sums as k_moments_level (leaves read twice).
-__global__ __launch_bounds__(1024) void k_moments_tail(MomArgs a, int l1) {
-    for (int l = kLevels - 2; l >= l1; --l) {
+__global__ __launch_bounds__(1024) void k_moments_tail(MomArgs a, int l0, int l1) {
+    for (int l = l0; l >= l1; --l) {
         const uint32_t first = a.c.ls[l], last = a.c.ls[l + 1];
         for (uint32_t i = first + threadIdx.x; i < last; i += 1024)
             cell_pass<false>(a, i, (uint32_t)l);
@@ -231,8 +231,9 @@ __global__ __launch_bounds__(1024) void k_moments_tail(MomArgs a, int l1) {
 
 // One pass per level from the deepest (leaves from their particles, parents
 // from their children, each cell's walk records as soon as its moments are
-// known): level 21 and the levels above grid_levels by one grid launch
-// each, the levels between by k_moments_tail.
+// known): the levels above grid_levels by one grid launch each, levels 21
+// down to grid_levels by k_moments_tail (level 21 by a grid launch too when
+// grid_levels is 21: no recent tree said the deep levels are sparse).
 void launch_moments(bh_ctx *ctx, hipStream_t st, int grid_levels) {
     const State &s = ctx->st[ctx->cur];
     MomArgs a;
@@ -242,8 +243,10 @@ void launch_moments(bh_ctx *ctx, hipStream_t st, int grid_levels) {
     a.box = ctx->box;
     a.curve = (int)ctx->p.curve;
     const int L = grid_levels < 0 ? 0 : (grid_levels > kLevels - 1 ? kLevels - 1 : grid_levels);
-    hipLaunchKernelGGL(k_moments_level, dim3(kGrid), dim3(256), 0, st, a, kLevels - 1);
-    if (L < kLevels - 1) hipLaunchKernelGGL(k_moments_tail, dim3(1), dim3(1024), 0, st, a, L);
+    if (L < kLevels - 1)
+        hipLaunchKernelGGL(k_moments_tail, dim3(1), dim3(1024), 0, st, a, kLevels - 1, L);
+    else
+        hipLaunchKernelGGL(k_moments_level, dim3(kGrid), dim3(256), 0, st, a, kLevels - 1);
     for (int l = L - 1; l >= 0; --l)
         hipLaunchKernelGGL(k_moments_level, dim3(kGrid), dim3(256), 0, st, a, l);
 }
