@@ -56,7 +56,7 @@ void free_all(bh_ctx *c) {
     f(c->sort.counts); f(c->sort.scan_part);
     Cells &q = c->cells;
     f(q.prefix); f(q.level); f(q.begin); f(q.count); f(q.child0); f(q.nchild); f(q.parent);
-    f(q.ls); f(q.part); f(q.lbt); f(q.M); f(q.S); f(q.com); f(q.Q); f(q.wA); f(q.wN); f(q.P0); f(q.P1);
+    f(q.ls); f(q.part); f(q.lbt); f(q.cbnd); f(q.M); f(q.S); f(q.com); f(q.Q); f(q.wA); f(q.wN); f(q.P0); f(q.P1);
     f(q.P2); f(q.size);
     Groups &g = c->groups;
     f(g.flag); f(g.scan); f(g.begin); f(g.count_dev); f(g.box); f(g.npp); f(g.npc);
@@ -300,6 +300,7 @@ size_t static_layout(bh_ctx *c, unsigned char *base) {
     take(&q.prefix, nc); take(&q.level, nc); take(&q.begin, nc); take(&q.count, nc);
     take(&q.child0, nc); take(&q.nchild, nc); take(&q.parent, nc); take(&q.ls, kLsSize);
     take(&q.part, kBuildGrid + 1); take(&q.lbt, ((size_t)1 << (3 * kTableLevel)) + 1);
+    take(&q.cbnd, 8 * n);
     take(&q.M, nc); take(&q.S, 3 * nc); take(&q.com, 3 * nc); take(&q.Q, 6 * nc);
     take(&q.wA, nc); take(&q.wN, nc); take(&q.P0, nc); take(&q.P1, nc); take(&q.P2, nc);
     take(&q.size, nc);
@@ -422,7 +423,7 @@ int bh_create(bh_ctx **out, int64_t n_max, const bh_params *p) {
          dalloc(&c->sort.scan_part, (size_t)c->sort.scan_part_len, err) &&
          dalloc(&q.prefix, nc, err) && dalloc(&q.level, nc, err) && dalloc(&q.begin, nc, err) &&
          dalloc(&q.count, nc, err) && dalloc(&q.child0, nc, err) && dalloc(&q.nchild, nc, err) &&
-         dalloc(&q.parent, nc, err) && dalloc(&q.ls, kLsSize, err) &&
+         dalloc(&q.parent, nc, err) && dalloc(&q.ls, kLsSize, err) && dalloc(&q.cbnd, 8 * n, err) &&
          dalloc(&q.part, kBuildGrid + 1, err) &&
          dalloc(&q.lbt, ((size_t)1 << (3 * kTableLevel)) + 1, err) && dalloc(&q.M, nc, err) && dalloc(&q.S, 3 * nc, err) &&
          dalloc(&q.com, 3 * nc, err) && dalloc(&q.Q, 6 * nc, err) && dalloc(&q.wA, nc, err) &&

@@ -54,6 +54,8 @@ struct Cells {
     uint32_t *ls;      // [kLsSize] level_start on the device
     uint32_t *part;    // [kBuildGrid + 1] per-block partials of the level scans
     uint32_t *lbt;     // [8^kTableLevel + 1] first sorted slot of every level-kTableLevel prefix
+    uint32_t *cbnd;    // [n_max][8] child bounds 1..8 of the cells of the level being split
+                       // (level-local index), from the count pass to the write pass
     // FP64 moments of the upward pass
     double *M, *S, *com, *Q;  // [c], [c][3], [c][3], [c][6]; com = S / M, filled for export
     // records read by the walk

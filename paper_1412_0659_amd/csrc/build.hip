@@ -97,11 +97,13 @@ __device__ __forceinline__ void level_chunk(const Cells &c, int l, uint32_t &cs,
 
 __global__ __launch_bounds__(kBuildThreads) void k_build_count(Cells c,
                                                                const uint64_t *__restrict__ key,
-                                                               int l, uint32_t nleaf) {
+                                                               int l, uint32_t nleaf,
+                                                               uint32_t nmax) {
     __shared__ uint32_t lds[4];
     uint32_t cs, ce;
     level_chunk(c, l, cs, ce);
-    const bool few = c.ls[l + 1] - c.ls[l] < kFewCells;
+    const uint32_t first = c.ls[l];
+    const bool few = c.ls[l + 1] - first < kFewCells;
     uint32_t sum = 0;
     for (uint32_t i = cs + threadIdx.x; i < ce; i += kBuildThreads) {
         uint32_t nch = 0;
@@ -112,6 +114,12 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_count(Cells c,
             child_bounds(key, c.lbt, c.prefix[i], b, b + cnt, l, few, bnd);
 #pragma unroll
             for (int d = 0; d < 8; ++d) nch += bnd[d + 1] > bnd[d];
+            // kept for the write pass (a level holds at most nmax cells)
+            if (i - first < nmax) {
+                uint4 *cb = reinterpret_cast<uint4 *>(c.cbnd + 8 * (size_t)(i - first));
+                cb[0] = make_uint4(bnd[1], bnd[2], bnd[3], bnd[4]);
+                cb[1] = make_uint4(bnd[5], bnd[6], bnd[7], bnd[8]);
+            }
         }
         c.nchild[i] = nch;
         sum += nch;
@@ -160,11 +168,13 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_scan(Cells c, int l, ui
 
 __global__ __launch_bounds__(kBuildThreads) void k_build_write(Cells c,
                                                                const uint64_t *__restrict__ key,
-                                                               int l, uint32_t cap) {
+                                                               int l, uint32_t cap,
+                                                               uint32_t nmax) {
     __shared__ uint32_t lds[4];
     uint32_t cs, ce;
     level_chunk(c, l, cs, ce);
-    const bool few = c.ls[l + 1] - c.ls[l] < kFewCells;
+    const uint32_t first = c.ls[l];
+    const bool few = c.ls[l + 1] - first < kFewCells;
     uint32_t carry = c.ls[l + 1] + c.part[blockIdx.x];
     uint32_t lane = lane_id(), w = threadIdx.x >> 6;
     for (uint32_t base = cs; base < ce; base += kBuildThreads) {
@@ -185,7 +195,15 @@ __global__ __launch_bounds__(kBuildThreads) void k_build_write(Cells c,
             uint32_t b = c.begin[i];
             uint64_t P = c.prefix[i];
             uint32_t bnd[9];
-            child_bounds(key, c.lbt, P, b, b + c.count[i], l, few, bnd);
+            if (i - first < nmax) {  // the bounds the count pass found
+                const uint4 *cb = reinterpret_cast<const uint4 *>(c.cbnd + 8 * (size_t)(i - first));
+                const uint4 u = cb[0], w = cb[1];
+                bnd[0] = b;
+                bnd[1] = u.x; bnd[2] = u.y; bnd[3] = u.z; bnd[4] = u.w;
+                bnd[5] = w.x; bnd[6] = w.y; bnd[7] = w.z; bnd[8] = w.w;
+            } else {
+                child_bounds(key, c.lbt, P, b, b + c.count[i], l, few, bnd);
+            }
             for (uint32_t d = 0; d < 8; ++d) {
                 if (bnd[d + 1] > bnd[d]) {
                     if (ch < cap) {
@@ -324,11 +342,12 @@ void launch_build(bh_ctx *ctx, uint32_t n, hipStream_t st, int grid_levels) {
     const int L = grid_levels < 0 ? 0 : (grid_levels > kLevels - 1 ? kLevels - 1 : grid_levels);
     for (int l = 0; l < L; ++l) {
         hipLaunchKernelGGL(k_build_count, dim3(kBuildGrid), dim3(kBuildThreads), 0, st, c,
-                           (const uint64_t *)ctx->sort.key[0], l, (uint32_t)ctx->p.nleaf);
+                           (const uint64_t *)ctx->sort.key[0], l, (uint32_t)ctx->p.nleaf,
+                           (uint32_t)ctx->nmax);
         hipLaunchKernelGGL(k_build_scan, dim3(1), dim3(kBuildThreads), 0, st, c, l, cap,
                            ctx->status);
         hipLaunchKernelGGL(k_build_write, dim3(kBuildGrid), dim3(kBuildThreads), 0, st, c,
-                           (const uint64_t *)ctx->sort.key[0], l, cap);
+                           (const uint64_t *)ctx->sort.key[0], l, cap, (uint32_t)ctx->nmax);
     }
     hipLaunchKernelGGL(k_build_tail, dim3(1), dim3(kTailThreads), 0, st, c,
                        (const uint64_t *)ctx->sort.key[0], L, (uint32_t)ctx->p.nleaf, cap,
