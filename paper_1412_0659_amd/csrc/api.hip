@@ -121,7 +121,6 @@ void rebuild(bh_ctx *c, uint32_t n, hipStream_t s, bool fresh) {
     record_event(c, 1, s);
     launch_build(c, n, s, L);
     launch_groups(c, n, s);
-    launch_count_leaves(c, s);
     record_event(c, 2, s);
     launch_moments(c, s, L);
     record_event(c, 3, s);
@@ -557,6 +556,7 @@ static double elapsed(bh_ctx *c, int a, int b) {
 int bh_stats_get(bh_ctx *c, bh_stats *out, hipStream_t s) {
     if (!c || !out) return BH_EINVAL;
     std::memset(out, 0, sizeof(*out));
+    if (c->built) launch_count_leaves(c, s);  // the leaves of the current tree, on demand
     BH_HIP(c, hipStreamSynchronize(s));
     out->n = c->n;
     if (c->built) {
@@ -573,7 +573,7 @@ int bh_stats_get(bh_ctx *c, bh_stats *out, hipStream_t s) {
             out->n_pp = (int64_t)tot[0];
             out->n_pc = (int64_t)tot[1];
         }
-        out->nleaves = (int64_t)tot[2];  // counted on the device by the build
+        out->nleaves = (int64_t)tot[2];  // counted on the device above
     }
     out->ms_sort = elapsed(c, 0, 1);
     out->ms_build = elapsed(c, 1, 2);

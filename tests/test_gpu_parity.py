@@ -47,6 +47,8 @@ def test_tree_bit_exact(oracle, name, pos, mass):
     size = t.export("cell_size")
     assert np.array_equal(size[:, 0], ot.mom["lf"]) and np.array_equal(size[:, 1], ot.mom["deltaf"])
     assert comf.shape[0] == nc
+    st = t.stats()
+    assert st["ncells"] == nc and st["nleaves"] == int((ot.cells["nchild"] == 0).sum())
     t.close()
 
 
