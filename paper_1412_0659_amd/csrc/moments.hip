@@ -23,8 +23,8 @@ namespace bh {
 
 // Leaves of at most kStage particles are read once into registers (the loads
 // issue together instead of one trip at a time) and summed from there; larger
-// leaves (nleaf > kStage, or the deepest level) read their particles twice.
-// The sums run in the same order either way.
+// leaves (nleaf > kStage) and the leaves of the single-workgroup tail read
+// their particles twice.  The sums run in the same order either way.
 constexpr uint32_t kStage = 16;
 
 struct MomArgs {
