@@ -150,16 +150,25 @@ __device__ __forceinline__ void parent_sums(const Cells &c, uint32_t k0, uint32_
     r = Mom{mm, s0, s1, s2, q0, q1, q2, q3, q4, q5};
 }
 
-// corner coordinates of a cell from its key prefix (x the high bit of each digit)
+// every third bit of v (bits 0, 3, 6, ...) gathered into the low 21 bits
+__device__ __forceinline__ uint32_t every_third_bit(uint64_t v) {
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10C30C30C30C30C3ull;
+    v = (v ^ (v >> 4)) & 0x100F00F00F00F00Full;
+    v = (v ^ (v >> 8)) & 0x001F0000FF0000FFull;
+    v = (v ^ (v >> 16)) & 0x001F00000000FFFFull;
+    v = (v ^ (v >> 32)) & 0x00000000001FFFFFull;
+    return (uint32_t)v;
+}
+
+// corner coordinates of a cell from its key prefix (x the high bit of each
+// 3-bit digit, the first digit the most significant); lev only bounds the
+// prefix, whose higher bits are zero
 __device__ __forceinline__ void cell_coords(uint64_t prefix, uint32_t lev, uint32_t p[3]) {
-    uint32_t a = 0, b = 0, d = 0;
-    for (int s = (int)lev - 1; s >= 0; --s) {
-        uint32_t dig = (uint32_t)(prefix >> (3 * s)) & 7u;
-        a = (a << 1) | (dig >> 2);
-        b = (b << 1) | ((dig >> 1) & 1u);
-        d = (d << 1) | (dig & 1u);
-    }
-    p[0] = a; p[1] = b; p[2] = d;
+    (void)lev;
+    p[0] = every_third_bit(prefix >> 2);
+    p[1] = every_third_bit(prefix >> 1);
+    p[2] = every_third_bit(prefix);
 }
 
 // Cell i of level lev: its FP64 moments (M, S, Q; the centre of mass is
